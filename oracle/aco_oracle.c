@@ -1,0 +1,570 @@
+/*
+ * CPU oracle for the ACO hot path -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, obviously correct reference of what the GPU path computes:
+ * Ant System tour construction with the random proportional rule (Eq. 1),
+ * evaporation (Eq. 2) and the all-ant 1/L deposit (Eq. 3-4), with pheromone
+ * stored only on each city's k nearest-neighbour candidate edges.
+ * Floating point is FP64 except where the method fixes FP32 (the stored
+ * pheromone and its update).  The fallback when every candidate is visited is
+ * an O(n) brute-force scan.  Nothing here is shared with the GPU library, and
+ * only the test suite, the smoke check and the benchmark's CPU baseline may
+ * load it.
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -fPIC -shared -pthread
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ */
+/* Distances (Section 2: complete graph with symmetric d_ij = d_ji).    */
+/* d_ij = nint(sqrt((xi-xj)^2 + (yi-yj)^2)), an integer.                */
+/* ------------------------------------------------------------------ */
+
+int64_t oracle_sq(const int32_t *xy, int64_t i, int64_t j)
+{
+    int64_t dx = (int64_t)xy[2 * i] - (int64_t)xy[2 * j];
+    int64_t dy = (int64_t)xy[2 * i + 1] - (int64_t)xy[2 * j + 1];
+    return dx * dx + dy * dy;
+}
+
+/* floor(sqrt(s)) exactly, for 0 <= s < 2^63. */
+static uint64_t isqrt_floor(uint64_t s)
+{
+    uint64_t r = (uint64_t)sqrt((double)s);
+    while (r * r > s) r--;
+    while ((r + 1) * (r + 1) <= s) r++;
+    return r;
+}
+
+/* nint(sqrt(s)): sqrt(s) >= r + 1/2  <=>  s > r^2 + r for integer s, r = floor(sqrt(s)).
+ * (sqrt(s) is never exactly r + 1/2 for integer s.) */
+int64_t oracle_nint_sqrt(int64_t s)
+{
+    uint64_t r = isqrt_floor((uint64_t)s);
+    return (int64_t)((uint64_t)s - r * r > r ? r + 1 : r);
+}
+
+int64_t oracle_dist(const int32_t *xy, int64_t i, int64_t j)
+{
+    return oracle_nint_sqrt(oracle_sq(xy, i, j));
+}
+
+int64_t oracle_tour_length(const int32_t *xy, int64_t n, const int32_t *tour)
+{
+    int64_t L = 0;
+    for (int64_t t = 0; t < n; t++) L += oracle_dist(xy, tour[t], tour[(t + 1) % n]);
+    return L;
+}
+
+/* ------------------------------------------------------------------ */
+/* Candidate lists (Section 6, the candidate-list idea of ACS: only the  */
+/* closest cities are considered).  nn[i] = the k smallest keys          */
+/* (d_ij, j) over j != i, ascending by distance then index.             */
+/* ------------------------------------------------------------------ */
+
+static int key_less(int64_t d1, int64_t j1, int64_t d2, int64_t j2)
+{
+    return d1 < d2 || (d1 == d2 && j1 < j2);
+}
+
+static void knn_row(const int32_t *xy, int64_t n, int k, int64_t i, int32_t *nn, int32_t *nnd)
+{
+    int cnt = 0;
+    for (int64_t j = 0; j < n; j++) {
+        if (j == i) continue;
+        int64_t d = oracle_dist(xy, i, j);
+        if (cnt == k && !key_less(d, j, nnd[k - 1], nn[k - 1])) continue;
+        int p = cnt < k ? cnt++ : k - 1;          /* insertion sort into the first k */
+        while (p > 0 && key_less(d, j, nnd[p - 1], nn[p - 1])) {
+            nn[p] = nn[p - 1];
+            nnd[p] = nnd[p - 1];
+            p--;
+        }
+        nn[p] = (int32_t)j;
+        nnd[p] = (int32_t)d;
+    }
+}
+
+/* Rows `rows[0..count)` of the candidate table; out arrays are [count][k]. */
+void oracle_knn_rows(const int32_t *xy, int64_t n, int k, const int32_t *rows, int64_t count,
+                     int32_t *nn, int32_t *nnd)
+{
+    for (int64_t q = 0; q < count; q++)
+        knn_row(xy, n, k, rows[q], nn + q * k, nnd + q * k);
+}
+
+/* rev[i][r] = position of i in nn[nn[i][r]], or -1 when i is not a candidate of nn[i][r]. */
+void oracle_rev(int64_t n, int k, const int32_t *nn, int8_t *rev)
+{
+    for (int64_t i = 0; i < n; i++)
+        for (int r = 0; r < k; r++) {
+            int64_t j = nn[i * k + r];
+            rev[i * k + r] = -1;
+            for (int s = 0; s < k; s++)
+                if (nn[j * k + s] == i) { rev[i * k + r] = (int8_t)s; break; }
+        }
+}
+
+/* ------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of the   */
+/* Philox S-box on a 4x32-bit counter with a 2x32-bit key bumped by the  */
+/* Weyl constants between rounds.                                        */
+/* ------------------------------------------------------------------ */
+
+void oracle_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; round++) {
+        if (round > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        uint32_t n1 = (uint32_t)p1;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        uint32_t n3 = (uint32_t)p0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* The colony's random word for (seed, iteration, ant, step):
+ * counter = (step, ant, iteration, 0), key = (seed low, seed high), word 0. */
+uint32_t oracle_draw(uint64_t seed, int64_t iteration, int64_t ant, int64_t step)
+{
+    uint32_t ctr[4] = {(uint32_t)step, (uint32_t)ant, (uint32_t)iteration, 0u};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    oracle_philox4x32_10(ctr, key, out);
+    return out[0];
+}
+
+/* Random start city (Section 2: ants start at a random city): (x * n) >> 32. */
+int64_t oracle_start_city(uint64_t seed, int64_t iteration, int64_t ant, int64_t n)
+{
+    return (int64_t)(((uint64_t)oracle_draw(seed, iteration, ant, 0) * (uint64_t)n) >> 32);
+}
+
+/* ------------------------------------------------------------------ */
+/* Fallback when every candidate of c is visited: the nearest unvisited */
+/* city, key (d_cj, j).  Brute force over all n cities.  Two passes:    */
+/* the smallest squared distance s_min fixes d* = nint(sqrt(s_min)); a  */
+/* city has d <= d* exactly when s <= d*^2 + d*, and the lowest index    */
+/* among those is the minimum key.                                      */
+/* ------------------------------------------------------------------ */
+
+static int64_t nearest_unvisited(const int32_t *xy, int64_t n, int64_t c, const uint8_t *vis,
+                                 int64_t *d_out)
+{
+    int64_t smin = -1;
+    for (int64_t j = 0; j < n; j++) {
+        if (vis[j]) continue;
+        int64_t s = oracle_sq(xy, c, j);
+        if (smin < 0 || s < smin) smin = s;
+    }
+    if (smin < 0) return -1;
+    int64_t dstar = oracle_nint_sqrt(smin);
+    int64_t thresh = dstar * dstar + dstar;
+    for (int64_t j = 0; j < n; j++)
+        if (!vis[j] && oracle_sq(xy, c, j) <= thresh) { *d_out = dstar; return j; }
+    return -1; /* unreachable */
+}
+
+/* Plain definition, for pinning the two-pass scan: argmin of (nint d, j). */
+int64_t oracle_nearest_unvisited_plain(const int32_t *xy, int64_t n, int64_t c, const uint8_t *vis)
+{
+    int64_t best = -1, bd = 0;
+    for (int64_t j = 0; j < n; j++) {
+        if (vis[j]) continue;
+        int64_t d = oracle_dist(xy, c, j);
+        if (best < 0 || d < bd) { best = j; bd = d; }
+    }
+    return best;
+}
+
+int64_t oracle_nearest_unvisited(const int32_t *xy, int64_t n, int64_t c, const uint8_t *vis)
+{
+    int64_t d;
+    return nearest_unvisited(xy, n, c, vis, &d);
+}
+
+/* ------------------------------------------------------------------ */
+/* Nearest-neighbour tour from city 0 (pheromone initialisation).       */
+/* Each step takes the unvisited city with the smallest (d, j).  Every  */
+/* candidate key is smaller than every non-candidate key, so the first  */
+/* unvisited entry of nn[c] is that city whenever one exists.           */
+/* ------------------------------------------------------------------ */
+
+int64_t oracle_nn_tour(const int32_t *xy, int64_t n, int k, const int32_t *nn, const int32_t *nnd,
+                       int32_t *tour)
+{
+    uint8_t *vis = (uint8_t *)calloc((size_t)n, 1);
+    int64_t c = 0, L = 0;
+    vis[0] = 1;
+    tour[0] = 0;
+    for (int64_t t = 1; t < n; t++) {
+        int64_t j = -1, d = 0;
+        for (int r = 0; r < k; r++)
+            if (!vis[nn[c * k + r]]) { j = nn[c * k + r]; d = nnd[c * k + r]; break; }
+        if (j < 0) j = nearest_unvisited(xy, n, c, vis, &d);
+        vis[j] = 1;
+        tour[t] = (int32_t)j;
+        L += d;
+        c = j;
+    }
+    L += oracle_dist(xy, c, 0);
+    free(vis);
+    return L;
+}
+
+/* The plain definition: argmin over all unvisited cities at every step (O(n^2)). */
+int64_t oracle_nn_tour_plain(const int32_t *xy, int64_t n, int32_t *tour)
+{
+    uint8_t *vis = (uint8_t *)calloc((size_t)n, 1);
+    int64_t c = 0;
+    vis[0] = 1;
+    tour[0] = 0;
+    for (int64_t t = 1; t < n; t++) {
+        int64_t j = oracle_nearest_unvisited_plain(xy, n, c, vis);
+        vis[j] = 1;
+        tour[t] = (int32_t)j;
+        c = j;
+    }
+    free(vis);
+    return oracle_tour_length(xy, n, tour);
+}
+
+/* Initial pheromone: tau0 = 1 / (n * L_nn), rounded once to FP32. */
+float oracle_tau0(int64_t n, int64_t L_nn)
+{
+    return (float)(1.0 / ((double)n * (double)L_nn));
+}
+
+/* ------------------------------------------------------------------ */
+/* Tour construction, Eq. 1 (random proportional rule).                 */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t n;
+    int k;
+    const int32_t *xy;
+    const int32_t *nn;
+    const int32_t *nnd;
+    const float *tau;        /* [n][k] FP32 pheromone */
+    const double *eta;       /* [n][k] heuristic override, or NULL for eta = 1/max(d,1) */
+    double alpha, beta;
+    uint64_t seed;
+    int64_t iteration;
+} colony_t;
+
+/* Heuristic eta_ir = 1/d_ir (Section 2); d = 0 (coincident cities) is read as 1. */
+static double eta_of(const colony_t *C, int64_t c, int r)
+{
+    if (C->eta) return C->eta[c * C->k + r];
+    int64_t d = C->nnd[c * C->k + r];
+    return 1.0 / (double)(d > 1 ? d : 1);
+}
+
+/* Weight tau^alpha * eta^beta of candidate r of city c, in FP64. */
+static double weight_of(const colony_t *C, int64_t c, int r)
+{
+    return pow((double)C->tau[c * C->k + r], C->alpha) * pow(eta_of(C, c, r), C->beta);
+}
+
+/* The roulette over the unvisited candidates of c.
+ * w[r] is the weight (0 for visited slots), cum[r] the running sum over
+ * unvisited slots in rank order.  Returns S = the total. */
+static double row_weights(const colony_t *C, int64_t c, const uint8_t *vis, double *w, double *cum,
+                          int *n_unvisited)
+{
+    double S = 0.0;
+    int nu = 0;
+    for (int r = 0; r < C->k; r++) {
+        int64_t j = C->nn[c * C->k + r];
+        w[r] = 0.0;
+        if (!vis[j]) { w[r] = weight_of(C, c, r); nu++; }
+        S += w[r];
+        cum[r] = S;
+    }
+    *n_unvisited = nu;
+    return S;
+}
+
+/* Pick the first unvisited slot with u*S < cum[r]; if rounding leaves none,
+ * the last slot with positive weight.  A zero-weight slot is never chosen. */
+static int roulette(const colony_t *C, const double *w, const double *cum, double S, double u)
+{
+    double target = u * S;
+    int last = -1;
+    for (int r = 0; r < C->k; r++) {
+        if (w[r] <= 0.0) continue;
+        if (target < cum[r]) return r;
+        last = r;
+    }
+    return last;
+}
+
+typedef struct {
+    int64_t length;
+    int64_t fallbacks;
+} ant_result_t;
+
+/* Build one ant's tour.  slot[t] = rank of tour[t] in nn[tour[t-1]] or -1 for a
+ * fallback move (slot[0] = -1); prob[t] = probability of the move (-1 for a fallback). */
+static ant_result_t construct_ant(const colony_t *C, int64_t ant, int32_t *tour, int8_t *slot,
+                                  double *prob)
+{
+    int64_t n = C->n;
+    int k = C->k;
+    uint8_t *vis = (uint8_t *)calloc((size_t)n, 1);
+    double w[64], cum[64];
+    ant_result_t res = {0, 0};
+    int64_t c = oracle_start_city(C->seed, C->iteration, ant, n);
+    int64_t start = c;
+    vis[c] = 1;
+    tour[0] = (int32_t)c;
+    if (slot) slot[0] = -1;
+    if (prob) prob[0] = 1.0;
+    for (int64_t t = 1; t < n; t++) {
+        double u = (double)oracle_draw(C->seed, C->iteration, ant, t) * 0x1p-32;
+        int nu;
+        double S = row_weights(C, c, vis, w, cum, &nu);
+        int64_t j, d;
+        if (nu > 0 && S > 0.0) {
+            int r = roulette(C, w, cum, S, u);
+            j = C->nn[c * k + r];
+            d = C->nnd[c * k + r];
+            if (slot) slot[t] = (int8_t)r;
+            if (prob) prob[t] = w[r] / S;
+        } else {
+            j = nearest_unvisited(C->xy, n, c, vis, &d);
+            res.fallbacks++;
+            if (slot) slot[t] = -1;
+            if (prob) prob[t] = -1.0;
+        }
+        vis[j] = 1;
+        tour[t] = (int32_t)j;
+        res.length += d;
+        c = j;
+    }
+    res.length += oracle_dist(C->xy, c, start);
+    free(vis);
+    return res;
+}
+
+/* Teacher-forced replay of a given tour.  At every step the oracle computes its
+ * own probabilities and choice, compares with the move the tour takes, and then
+ * follows the given tour.  Counters (out[0..7]):
+ *   0 steps checked, 1 fallback steps, 2 choice mismatches at a near boundary
+ *   (|u - C_r/S| < boundary_eps for some unvisited r), 3 hard mismatches,
+ *   4 fallback mismatches, 5 invalid moves (revisit / out of range / wrong start),
+ *   6 steps where u is within boundary_eps of a cumulative boundary (any outcome).
+ * prob[t] receives the oracle's probability of the move the tour takes
+ * (-1 for a fallback step, 0 if the move has zero probability). */
+void oracle_replay_ant(const colony_t *C, int64_t ant, const int32_t *tour, double boundary_eps,
+                       double *prob, int64_t *out)
+{
+    int64_t n = C->n;
+    int k = C->k;
+    uint8_t *vis = (uint8_t *)calloc((size_t)n, 1);
+    double w[64], cum[64];
+    memset(out, 0, 8 * sizeof(int64_t));
+    int64_t c = tour[0];
+    if (c != oracle_start_city(C->seed, C->iteration, ant, n)) out[5]++;
+    if (c < 0 || c >= n) { out[5]++; free(vis); return; }
+    vis[c] = 1;
+    prob[0] = 1.0;
+    for (int64_t t = 1; t < n; t++) {
+        int64_t j = tour[t];
+        out[0]++;
+        if (j < 0 || j >= n || vis[j]) { out[5]++; prob[t] = 0.0; break; }
+        double u = (double)oracle_draw(C->seed, C->iteration, ant, t) * 0x1p-32;
+        int nu;
+        double S = row_weights(C, c, vis, w, cum, &nu);
+        if (nu > 0 && S > 0.0) {
+            int r = roulette(C, w, cum, S, u);
+            int taken = -1;
+            for (int q = 0; q < k; q++)
+                if (C->nn[c * k + q] == j) taken = q;
+            prob[t] = (taken >= 0) ? w[taken] / S : 0.0;
+            int near = 0;
+            for (int q = 0; q < k; q++)
+                if (w[q] > 0.0 && fabs(u - cum[q] / S) < boundary_eps) near = 1;
+            if (near) out[6]++;
+            if (taken != r) {
+                if (near && taken >= 0 && w[taken] > 0.0) out[2]++;
+                else out[3]++;
+            }
+        } else {
+            int64_t d;
+            out[1]++;
+            prob[t] = -1.0;
+            if (nearest_unvisited(C->xy, n, c, vis, &d) != j) out[4]++;
+        }
+        vis[j] = 1;
+        c = j;
+    }
+    free(vis);
+}
+
+/* ------------------------------------------------------------------ */
+/* Pheromone update: evaporation (Eq. 2) then the deposit of every ant  */
+/* (Eq. 3-4), Delta tau = 1/C^k on the edges of ant k's tour, quantised  */
+/* to int64 fixed point q = floor(2^shift / L) and accumulated exactly. */
+/* Each undirected edge {i,j} is stored as up to two directed slots      */
+/* (j in nn[i], i in nn[j]); both get the deposit, absent slots nothing. */
+/* ------------------------------------------------------------------ */
+
+void oracle_deposit(int64_t n, int k, const int32_t *nn, int64_t m, const int32_t *tours,
+                    const int64_t *lengths, int shift, int64_t *acc)
+{
+    memset(acc, 0, (size_t)(n * k) * sizeof(int64_t));
+    for (int64_t a = 0; a < m; a++) {
+        int64_t q = ((int64_t)1 << shift) / lengths[a];
+        const int32_t *T = tours + a * n;
+        for (int64_t t = 0; t < n; t++) {
+            int64_t i = T[t], j = T[(t + 1) % n];
+            for (int r = 0; r < k; r++)
+                if (nn[i * k + r] == j) acc[i * k + r] += q;
+            for (int r = 0; r < k; r++)
+                if (nn[j * k + r] == i) acc[j * k + r] += q;
+        }
+    }
+}
+
+void oracle_update(int64_t n, int k, const int32_t *nn, float *tau, int64_t m, const int32_t *tours,
+                   const int64_t *lengths, double rho, int shift)
+{
+    int64_t *acc = (int64_t *)malloc((size_t)(n * k) * sizeof(int64_t));
+    oracle_deposit(n, k, nn, m, tours, lengths, shift, acc);
+    float f = (float)(1.0 - rho);
+    float scale = ldexpf(1.0f, -shift);
+    for (int64_t e = 0; e < n * k; e++) {
+        float evap = tau[e] * f;                       /* Eq. 2, FP32 */
+        float dep = (float)acc[e] * scale;             /* exact power-of-two scaling */
+        tau[e] = evap + dep;                           /* Eq. 3, one FP32 rounding */
+    }
+    free(acc);
+}
+
+/* ------------------------------------------------------------------ */
+/* Construction of many ants, threads over ants.                        */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    const colony_t *C;
+    const int64_t *ants;
+    int64_t count;
+    int32_t *tours;
+    int64_t *lengths;
+    int8_t *slots;
+    double *probs;
+    int64_t *fallbacks;
+    int64_t next;
+    pthread_mutex_t lock;
+} pool_t;
+
+static void *construct_worker(void *arg)
+{
+    pool_t *P = (pool_t *)arg;
+    int64_t n = P->C->n;
+    for (;;) {
+        pthread_mutex_lock(&P->lock);
+        int64_t q = P->next++;
+        pthread_mutex_unlock(&P->lock);
+        if (q >= P->count) break;
+        ant_result_t r = construct_ant(P->C, P->ants[q], P->tours + q * n,
+                                       P->slots ? P->slots + q * n : NULL,
+                                       P->probs ? P->probs + q * n : NULL);
+        P->lengths[q] = r.length;
+        if (P->fallbacks) P->fallbacks[q] = r.fallbacks;
+    }
+    return NULL;
+}
+
+static void colony_init(colony_t *C, int64_t n, int k, const int32_t *xy, const int32_t *nn,
+                        const int32_t *nnd, const float *tau, const double *eta, double alpha,
+                        double beta, uint64_t seed, int64_t iteration)
+{
+    C->n = n; C->k = k; C->xy = xy; C->nn = nn; C->nnd = nnd; C->tau = tau; C->eta = eta;
+    C->alpha = alpha; C->beta = beta; C->seed = seed; C->iteration = iteration;
+}
+
+/* Construct the ants listed in `ants` (count of them); outputs are [count][n]. */
+void oracle_construct(int64_t n, int k, const int32_t *xy, const int32_t *nn, const int32_t *nnd,
+                      const float *tau, const double *eta, double alpha, double beta, uint64_t seed,
+                      int64_t iteration, const int64_t *ants, int64_t count, int32_t *tours,
+                      int64_t *lengths, int8_t *slots, double *probs, int64_t *fallbacks,
+                      int threads)
+{
+    colony_t C;
+    colony_init(&C, n, k, xy, nn, nnd, tau, eta, alpha, beta, seed, iteration);
+    pool_t P = {&C, ants, count, tours, lengths, slots, probs, fallbacks, 0,
+                PTHREAD_MUTEX_INITIALIZER};
+    if (threads < 1) threads = 1;
+    if (threads > 256) threads = 256;
+    pthread_t th[256];
+    for (int t = 0; t < threads; t++) pthread_create(&th[t], NULL, construct_worker, &P);
+    for (int t = 0; t < threads; t++) pthread_join(th[t], NULL);
+}
+
+void oracle_replay(int64_t n, int k, const int32_t *xy, const int32_t *nn, const int32_t *nnd,
+                   const float *tau, const double *eta, double alpha, double beta, uint64_t seed,
+                   int64_t iteration, int64_t ant, const int32_t *tour, double boundary_eps,
+                   double *prob, int64_t *out)
+{
+    colony_t C;
+    colony_init(&C, n, k, xy, nn, nnd, tau, eta, alpha, beta, seed, iteration);
+    oracle_replay_ant(&C, ant, tour, boundary_eps, prob, out);
+}
+
+/* ------------------------------------------------------------------ */
+/* The whole loop for one instance: candidates, NN-tour initialisation, */
+/* then `iterations` rounds of construction and update.  The iteration  */
+/* best is the shortest tour (lowest ant on ties); the global best is   */
+/* replaced only by a strictly shorter tour.                            */
+/* ------------------------------------------------------------------ */
+
+int oracle_run(int64_t n, int k, const int32_t *xy, int64_t m, double alpha, double beta, double rho,
+               int64_t iterations, uint64_t seed, int shift, int threads, int32_t *best_tour,
+               int64_t *best_len, int64_t *iter_best, float *tau_out)
+{
+    int32_t *nn = (int32_t *)malloc((size_t)(n * k) * 4);
+    int32_t *nnd = (int32_t *)malloc((size_t)(n * k) * 4);
+    int32_t *rows = (int32_t *)malloc((size_t)n * 4);
+    float *tau = (float *)malloc((size_t)(n * k) * 4);
+    int32_t *tours = (int32_t *)malloc((size_t)(m * n) * 4);
+    int64_t *lengths = (int64_t *)malloc((size_t)m * 8);
+    int64_t *ants = (int64_t *)malloc((size_t)m * 8);
+    for (int64_t i = 0; i < n; i++) rows[i] = (int32_t)i;
+    oracle_knn_rows(xy, n, k, rows, n, nn, nnd);
+    int64_t Lnn = oracle_nn_tour(xy, n, k, nn, nnd, best_tour);
+    if (Lnn <= 0) {
+        free(nn); free(nnd); free(rows); free(tau); free(tours); free(lengths); free(ants);
+        return -3;   /* every city coincident: tau0 undefined */
+    }
+    *best_len = Lnn;   /* best so far starts as the NN tour */
+    float t0 = oracle_tau0(n, Lnn);
+    for (int64_t e = 0; e < n * k; e++) tau[e] = t0;
+    for (int64_t a = 0; a < m; a++) ants[a] = a;
+    for (int64_t it = 0; it < iterations; it++) {
+        oracle_construct(n, k, xy, nn, nnd, tau, NULL, alpha, beta, seed, it, ants, m, tours,
+                         lengths, NULL, NULL, NULL, threads);
+        int64_t ib = 0;
+        for (int64_t a = 1; a < m; a++)
+            if (lengths[a] < lengths[ib]) ib = a;
+        if (iter_best) iter_best[it] = lengths[ib];
+        if (lengths[ib] < *best_len) {
+            *best_len = lengths[ib];
+            memcpy(best_tour, tours + ib * n, (size_t)n * 4);
+        }
+        oracle_update(n, k, nn, tau, m, tours, lengths, rho, shift);
+    }
+    if (tau_out) memcpy(tau_out, tau, (size_t)(n * k) * 4);
+    free(nn); free(nnd); free(rows); free(tau); free(tours); free(lengths); free(ants);
+    return 0;
+}
