@@ -1,0 +1,197 @@
+/*
+ * aco.h -- C ABI of the MI355X ACO hot-path library (libaco.so).
+ *
+ * Ant colony optimisation for the symmetric TSP (Chitty, "Applying ACO To
+ * Large Scale TSP Instances", Section 2): m ants build tours with the random
+ * proportional rule (Eq. 1), then the pheromone is evaporated (Eq. 2) and
+ * every ant deposits 1/C^k on the edges of its tour (Eq. 3-4).  Pheromone is
+ * held only on each city's k nearest-neighbour candidate edges (an n x k
+ * table instead of the n x n matrix whose size Section 3 identifies as the
+ * obstacle to large instances; candidate lists are the ACS device recalled in
+ * Section 6).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Array arguments are DEVICE pointers into memory owned by the caller
+ *   (e.g. torch tensors); host pointers are marked "host".  Row-major layouts,
+ *   no padding.  The library keeps no pointer after a call returns, but the
+ *   work it enqueued reads and writes the buffers until the stream reaches it.
+ * - `stream` is a hipStream_t (NULL = the legacy default stream).  All work is
+ *   enqueued on it in order; entry points marked "synchronises" wait for it.
+ * - Return value: ACO_OK (0) or a negative ACO_ERR_* code.  Arguments are
+ *   validated on the host before anything is enqueued: on a validation error
+ *   nothing is launched and the outputs are untouched.  aco_last_error()
+ *   returns a thread-local message for the most recent failure.
+ * - Cities are numbered 0..n-1 in input order; "index" always means that
+ *   number.  Distances are d_ij = nint(sqrt((xi-xj)^2 + (yi-yj)^2)) (Section
+ *   2 requires only d_ij = d_ji; the rounded Euclidean form is the TSPLIB
+ *   EUC_2D convention), computed exactly in integers.
+ * - Coordinates must satisfy |x|, |y| <= ACO_COORD_LIMIT.
+ * - Random numbers: Philox4x32-10 with key (seed low 32 bits, seed high 32
+ *   bits) and counter (step, ant, iteration, 0); word 0 is used.  Step 0 draws
+ *   the start city (x * n) >> 32 (Section 2: ants start at a random city);
+ *   step t >= 1 draws u = x * 2^-32 for the roulette of Eq. 1.
+ */
+#ifndef ACO_H
+#define ACO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ACO_OK 0
+#define ACO_ERR_INVALID_ARG (-1) /* a size, pointer or parameter is out of range */
+#define ACO_ERR_UNSUPPORTED (-2) /* valid, but beyond what this build supports (e.g. LDS) */
+#define ACO_ERR_DEGENERATE (-3)  /* every city coincides: the NN tour has length 0 */
+#define ACO_ERR_WORKSPACE (-4)   /* workspace smaller than the matching *_bytes query */
+#define ACO_ERR_HIP (-5)         /* a HIP runtime call failed */
+
+#define ACO_COORD_LIMIT 536870911 /* 2^29 - 1: every distance fits in int32 */
+#define ACO_MAX_K 64               /* one candidate per lane of a 64-wide wavefront */
+
+/* Human-readable name of an ACO_* code (static string). */
+const char *aco_strerror(int code);
+/* Message describing the last failure on the calling thread ("" if none). */
+const char *aco_last_error(void);
+/* Library version string. */
+const char *aco_version(void);
+
+/* ------------------------------------------------------------------------
+ * Candidate lists and spatial grid.
+ *
+ * For every city i: nn[i][r], r = 0..k-1, are the k cities j != i with the
+ * smallest keys (d_ij, j), ascending (distance, then index); nnd[i][r] =
+ * d_{i,nn[i][r]}; rev[i][r] = the position of i in nn[nn[i][r]] or -1;
+ * eta_b[i][r] = eta^beta rounded once to FP32, with eta = 1/max(d, 1) (Section
+ * 2: eta_ij = 1/d_ij; coincident cities read as d = 1) or, when `eta` is not
+ * NULL, eta = eta[i][r] (a learned heuristic score > 0, FP32 [n][k]).
+ *
+ * The grid (uniform square cells, about two cities per cell) serves the
+ * nearest-unvisited fallback.  It is an opaque device buffer of
+ * aco_grid_bytes(n) bytes written here and read by the other entry points.
+ *
+ *   xy     int32 [n][2]   coordinates (x, y)
+ *   n      3 <= n <= 2^27;  k: 1 <= k <= min(n-1, ACO_MAX_K);  beta >= 0, finite
+ *   nn, nnd int32 [n][k]; rev int8 [n][k]; eta_b float [n][k]   (outputs)
+ * Synchronises (reads back the bounding box to size the grid).
+ * Errors: INVALID_ARG (sizes, NULL pointers, |coord| > ACO_COORD_LIMIT),
+ *         DEGENERATE (all cities coincide), WORKSPACE (grid_bytes too small).
+ * ------------------------------------------------------------------------ */
+size_t aco_grid_bytes(int32_t n);
+int aco_build_candidates(const int32_t *xy, int32_t n, int32_t k, double beta, const float *eta,
+                         int32_t *nn, int32_t *nnd, int8_t *rev, float *eta_b, void *grid,
+                         size_t grid_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Pheromone initialisation: the nearest-neighbour tour from city 0 (each step
+ * takes the unvisited city of smallest (d, j)), its length L_nn, and
+ * tau[i][r] = tau0 = fl32(1 / (n * L_nn)) for every candidate slot.
+ *
+ *   grid      the buffer from aco_build_candidates (8 bytes of its header
+ *             block are used as scratch for the tour length)
+ *   nn_tour   int32 [n] (output)   tau float [n][k] (output)
+ *   tau0_out  host float* (output, may be NULL); L_nn_out host int64* (may be NULL)
+ * Synchronises.  Errors: INVALID_ARG, DEGENERATE (L_nn == 0), UNSUPPORTED
+ * (visited bitmask of ceil(n/32) words does not fit in LDS).
+ * ------------------------------------------------------------------------ */
+int aco_init_pheromone(const int32_t *xy, int32_t n, int32_t k, const int32_t *nn,
+                       const int32_t *nnd, void *grid, int32_t *nn_tour, float *tau,
+                       float *tau0_out, int64_t *L_nn_out, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Tour construction (Section 2, Eq. 1).  Ant a (0 <= a < m) starts at
+ * (x * n) >> 32 and at every later step, standing at city c, considers the
+ * unvisited candidates r of c in rank order with weights
+ *     w_r = tau[c][r]^alpha * eta_b[c][r]
+ * and moves to the first r with u * S < C_r, S the total weight and C_r the
+ * running sum (a zero-weight candidate is never chosen).  When no unvisited
+ * candidate has positive weight the ant moves to the nearest unvisited city
+ * (smallest (d, j)), found exactly on the grid.
+ *
+ *   tau      float [n][k]  pheromone (read)
+ *   ant0     index of the first ant (ants ant0..ant0+m-1 are built; the
+ *            Philox counter uses the absolute ant index)
+ *   tours    int32 [m][n]  (output) city order, tours[a][0] = start city
+ *   lengths  int64 [m]     (output) closed tour length C^a
+ *   slots    uint8 [m][n]  (output) slots[a][t] = rank r of tours[a][t] in
+ *            nn[tours[a][t-1]], 255 for a fallback move; slots[a][0] = 255
+ *   step_prob float [m][n] (output, may be NULL) probability of the move
+ *            taken at step t (-1 for a fallback move; 1 at t = 0)
+ *   ws       device workspace of aco_construct_workspace_bytes(n, k) bytes
+ * Constraints: 0 <= iteration < 2^32, m >= 1, alpha >= 0 finite.
+ * Errors: INVALID_ARG, WORKSPACE, UNSUPPORTED (bitmask does not fit in LDS).
+ * ------------------------------------------------------------------------ */
+size_t aco_construct_workspace_bytes(int32_t n, int32_t k);
+int aco_construct_tours(const int32_t *xy, int32_t n, int32_t k, const int32_t *nn,
+                        const int32_t *nnd, const float *eta_b, const void *grid, const float *tau,
+                        int32_t m, int32_t ant0, double alpha, uint64_t seed, int64_t iteration,
+                        int32_t *tours, int64_t *lengths, uint8_t *slots, float *step_prob,
+                        void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Pheromone update.  Evaporation tau' = fl32(tau * fl32(1 - rho)) on every
+ * candidate slot (Eq. 2), then the deposit of every ant (Eq. 3-4): ant a adds
+ * q_a = floor(2^deposit_shift / lengths[a]) (1/C^a in fixed point) to each
+ * directed slot (i, r) with nn[i][r] = j for every edge {i, j} of its tour,
+ * the closing edge included, in both directions when both slots exist; edges
+ * outside the candidate lists carry no pheromone.  Sums are exact in int64,
+ * and the merge is tau = fl32(tau' + fl32(acc) * 2^-deposit_shift).
+ *
+ *   tours int32 [m][n] (any permutations), slots uint8 [m][n] from
+ *   aco_construct_tours or NULL (then every edge is located by scanning the
+ *   candidate rows), lengths int64 [m] > 0, 0 < rho <= 1,
+ *   0 <= deposit_shift <= 62 (the caller keeps m * 2^shift / min L < 2^63),
+ *   tau float [n][k] (in/out), ws: aco_update_workspace_bytes(n, k, m) bytes.
+ * Errors: INVALID_ARG, WORKSPACE.
+ * ------------------------------------------------------------------------ */
+size_t aco_update_workspace_bytes(int32_t n, int32_t k, int32_t m);
+int aco_update_pheromone(int32_t n, int32_t k, const int32_t *nn, const int8_t *rev, int32_t m,
+                         const int32_t *tours, const uint8_t *slots, const int64_t *lengths,
+                         double rho, int32_t deposit_shift, float *tau, void *ws, size_t ws_bytes,
+                         void *stream);
+
+/* ------------------------------------------------------------------------
+ * Best-tour tracking (the method outputs the best tour found, Alg. 1's last
+ * step).  The iteration best is the shortest of lengths[0..m) (lowest ant on
+ * ties); it replaces the best so far only when strictly shorter.
+ *
+ *   best_len   int64 [1] (in/out, device)   best_tour int32 [n] (in/out)
+ *   iter_best  int64 [1] (output, device; may be NULL)
+ * ------------------------------------------------------------------------ */
+int aco_track_best(int32_t n, int32_t m, const int32_t *tours, const int64_t *lengths,
+                   int64_t *best_len, int32_t *best_tour, int64_t *iter_best, void *stream);
+
+/* ------------------------------------------------------------------------
+ * The whole loop on one instance: candidates, NN-tour initialisation (the
+ * best so far starts as the NN tour), then `iterations` rounds of
+ * construction (iteration t uses the pheromone after t updates), update and
+ * best tracking.
+ * ------------------------------------------------------------------------ */
+typedef struct aco_params {
+    int32_t m;             /* ants per iteration, >= 1 */
+    int32_t k;             /* candidates per city */
+    double alpha;          /* pheromone exponent, >= 0 */
+    double beta;           /* heuristic exponent, >= 0 */
+    double rho;            /* evaporation rate, 0 < rho <= 1 */
+    int32_t iterations;    /* >= 0 */
+    int32_t deposit_shift; /* fixed-point fraction bits of the deposit, 0..62 (32) */
+    uint64_t seed;         /* Philox key */
+} aco_params_t;
+
+size_t aco_run_workspace_bytes(int32_t n, const aco_params_t *p);
+/*   best_tour int32 [n], best_len int64 [1] (outputs, device)
+ *   iter_best int64 [iterations] (output, may be NULL)
+ *   tau_out   float [n][k] final pheromone (output, may be NULL)
+ * Synchronises (during set-up).  Errors: as the steps above. */
+int aco_run(const int32_t *xy, int32_t n, const aco_params_t *p, int32_t *best_tour,
+            int64_t *best_len, int64_t *iter_best, float *tau_out, void *ws, size_t ws_bytes,
+            void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ACO_H */

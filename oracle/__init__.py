@@ -64,6 +64,7 @@ def lib():
             "oracle_dist": (i64, [p, i64, i64]),
             "oracle_tour_length": (i64, [p, i64, p]),
             "oracle_knn_rows": (None, [p, i64, C.c_int, p, i64, p, p]),
+            "oracle_knn_rows_mt": (None, [p, i64, C.c_int, p, i64, p, p, C.c_int]),
             "oracle_rev": (None, [i64, C.c_int, p, p]),
             "oracle_philox4x32_10": (None, [p, p, p]),
             "oracle_draw": (C.c_uint32, [u64, i64, i64, i64]),
@@ -121,7 +122,7 @@ def tour_length(xy, tour) -> int:
 
 
 # ---------------------------------------------------------------- candidates
-def knn_rows(xy, k: int, rows=None):
+def knn_rows(xy, k: int, rows=None, threads=1):
     """(nn, nnd) int32 [len(rows)][k] for the requested cities (default: all)."""
     xy = _xy(xy)
     n = len(xy)
@@ -129,7 +130,11 @@ def knn_rows(xy, k: int, rows=None):
     rows = np.arange(n, dtype=np.int32) if rows is None else np.ascontiguousarray(rows, np.int32)
     nn = np.empty((len(rows), k), np.int32)
     nnd = np.empty((len(rows), k), np.int32)
-    lib().oracle_knn_rows(_p(xy), n, k, _p(rows), len(rows), _p(nn), _p(nnd))
+    if threads == 1:
+        lib().oracle_knn_rows(_p(xy), n, k, _p(rows), len(rows), _p(nn), _p(nnd))
+    else:
+        lib().oracle_knn_rows_mt(_p(xy), n, k, _p(rows), len(rows), _p(nn), _p(nnd),
+                                 _threads(threads))
     return nn, nnd
 
 

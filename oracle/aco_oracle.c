@@ -97,6 +97,39 @@ void oracle_knn_rows(const int32_t *xy, int64_t n, int k, const int32_t *rows, i
         knn_row(xy, n, k, rows[q], nn + q * k, nnd + q * k);
 }
 
+typedef struct {
+    const int32_t *xy;
+    int64_t n;
+    int k;
+    const int32_t *rows;
+    int64_t lo, hi;
+    int32_t *nn, *nnd;
+} knn_job_t;
+
+static void *knn_worker(void *arg)
+{
+    knn_job_t *J = (knn_job_t *)arg;
+    for (int64_t q = J->lo; q < J->hi; q++)
+        knn_row(J->xy, J->n, J->k, J->rows[q], J->nn + q * J->k, J->nnd + q * J->k);
+    return NULL;
+}
+
+/* The same rows split over `threads` threads (contiguous blocks of rows). */
+void oracle_knn_rows_mt(const int32_t *xy, int64_t n, int k, const int32_t *rows, int64_t count,
+                        int32_t *nn, int32_t *nnd, int threads)
+{
+    if (threads < 1) threads = 1;
+    if (threads > 256) threads = 256;
+    pthread_t th[256];
+    knn_job_t jobs[256];
+    for (int t = 0; t < threads; t++) {
+        jobs[t] = (knn_job_t){xy, n, k, rows, count * t / threads, count * (t + 1) / threads,
+                              nn, nnd};
+        pthread_create(&th[t], NULL, knn_worker, &jobs[t]);
+    }
+    for (int t = 0; t < threads; t++) pthread_join(th[t], NULL);
+}
+
 /* rev[i][r] = position of i in nn[nn[i][r]], or -1 when i is not a candidate of nn[i][r]. */
 void oracle_rev(int64_t n, int k, const int32_t *nn, int8_t *rev)
 {

@@ -1,0 +1,276 @@
+"""Python binding of libaco.so, the MI355X ACO hot-path library.
+
+Argument marshalling only: every step runs in the library's HIP kernels.  The
+functions keep the C entry points' names; arrays are torch tensors on the GPU
+(their `data_ptr()` is passed through) and the stream defaults to torch's
+current stream.  `Colony` is a convenience holder that allocates the device
+buffers of one instance with torch and calls the entry points in order.
+
+The library must have been built (`python -m paper_1709_03187_amd.build`);
+importing a function that needs it raises if `libaco.so` is missing -- there
+is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libaco.so")
+_lib = None
+
+ACO_OK = 0
+ACO_ERR_INVALID_ARG = -1
+ACO_ERR_UNSUPPORTED = -2
+ACO_ERR_DEGENERATE = -3
+ACO_ERR_WORKSPACE = -4
+ACO_ERR_HIP = -5
+ACO_COORD_LIMIT = 2**29 - 1
+ACO_MAX_K = 64
+NO_SLOT = 255
+
+EXPORTS = (
+    "aco_strerror", "aco_last_error", "aco_version", "aco_grid_bytes", "aco_build_candidates",
+    "aco_init_pheromone", "aco_construct_workspace_bytes", "aco_construct_tours",
+    "aco_update_workspace_bytes", "aco_update_pheromone", "aco_track_best",
+    "aco_run_workspace_bytes", "aco_run",
+)
+
+
+class AcoError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class AcoParams(C.Structure):
+    _fields_ = [("m", C.c_int32), ("k", C.c_int32), ("alpha", C.c_double),
+                ("beta", C.c_double), ("rho", C.c_double), ("iterations", C.c_int32),
+                ("deposit_shift", C.c_int32), ("seed", C.c_uint64)]
+
+
+def lib():
+    """Load libaco.so (after torch, so both share torch's HIP runtime)."""
+    global _lib
+    if _lib is None:
+        import torch  # noqa: F401  -- loads the HIP runtime the library binds to
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_1709_03187_amd.build")
+        L = C.CDLL(LIB_PATH)
+        p, i32, i64, u64, dbl, sz = (C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double,
+                                     C.c_size_t)
+        sig = {
+            "aco_strerror": (C.c_char_p, [C.c_int]),
+            "aco_last_error": (C.c_char_p, []),
+            "aco_version": (C.c_char_p, []),
+            "aco_grid_bytes": (sz, [i32]),
+            "aco_build_candidates": (C.c_int, [p, i32, i32, dbl, p, p, p, p, p, p, sz, p]),
+            "aco_init_pheromone": (C.c_int, [p, i32, i32, p, p, p, p, p, p, p, p]),
+            "aco_construct_workspace_bytes": (sz, [i32, i32]),
+            "aco_construct_tours": (C.c_int, [p, i32, i32, p, p, p, p, p, i32, i32, dbl, u64,
+                                              i64, p, p, p, p, p, sz, p]),
+            "aco_update_workspace_bytes": (sz, [i32, i32, i32]),
+            "aco_update_pheromone": (C.c_int, [i32, i32, p, p, i32, p, p, p, dbl, i32, p, p, sz,
+                                               p]),
+            "aco_track_best": (C.c_int, [i32, i32, p, p, p, p, p, p]),
+            "aco_run_workspace_bytes": (sz, [i32, C.POINTER(AcoParams)]),
+            "aco_run": (C.c_int, [p, i32, C.POINTER(AcoParams), p, p, p, p, p, sz, p]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype, f.argtypes = res, args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != ACO_OK:
+        L = lib()
+        raise AcoError(rc, f"{L.aco_strerror(rc).decode()}: {L.aco_last_error().decode()}")
+
+
+def _ptr(t, dtype=None, name="array"):
+    if t is None:
+        return None
+    import torch
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _t():
+    import torch
+    return torch
+
+
+# ------------------------------------------------------------ entry points
+def aco_version() -> str:
+    return lib().aco_version().decode()
+
+
+def aco_grid_bytes(n: int) -> int:
+    return int(lib().aco_grid_bytes(n))
+
+
+def aco_construct_workspace_bytes(n: int, k: int) -> int:
+    return int(lib().aco_construct_workspace_bytes(n, k))
+
+
+def aco_update_workspace_bytes(n: int, k: int, m: int) -> int:
+    return int(lib().aco_update_workspace_bytes(n, k, m))
+
+
+def aco_run_workspace_bytes(n: int, params: AcoParams) -> int:
+    return int(lib().aco_run_workspace_bytes(n, C.byref(params)))
+
+
+def aco_build_candidates(xy, n, k, beta, eta, nn, nnd, rev, eta_b, grid, stream=None):
+    torch = _t()
+    _check(lib().aco_build_candidates(
+        _ptr(xy, torch.int32, "xy"), n, k, float(beta), _ptr(eta, torch.float32, "eta"),
+        _ptr(nn, torch.int32, "nn"), _ptr(nnd, torch.int32, "nnd"), _ptr(rev, torch.int8, "rev"),
+        _ptr(eta_b, torch.float32, "eta_b"), _ptr(grid, torch.uint8, "grid"), grid.numel(),
+        _stream(stream)))
+
+
+def aco_init_pheromone(xy, n, k, nn, nnd, grid, nn_tour, tau, stream=None):
+    """Returns (tau0, L_nn)."""
+    torch = _t()
+    t0 = C.c_float(0)
+    L = C.c_int64(0)
+    _check(lib().aco_init_pheromone(
+        _ptr(xy, torch.int32, "xy"), n, k, _ptr(nn, torch.int32, "nn"),
+        _ptr(nnd, torch.int32, "nnd"), _ptr(grid, torch.uint8, "grid"),
+        _ptr(nn_tour, torch.int32, "nn_tour"), _ptr(tau, torch.float32, "tau"), C.byref(t0),
+        C.byref(L), _stream(stream)))
+    return t0.value, L.value
+
+
+def aco_construct_tours(xy, n, k, nn, nnd, eta_b, grid, tau, m, ant0, alpha, seed, iteration,
+                        tours, lengths, slots, step_prob, ws, stream=None):
+    torch = _t()
+    _check(lib().aco_construct_tours(
+        _ptr(xy, torch.int32, "xy"), n, k, _ptr(nn, torch.int32, "nn"),
+        _ptr(nnd, torch.int32, "nnd"), _ptr(eta_b, torch.float32, "eta_b"),
+        _ptr(grid, torch.uint8, "grid"), _ptr(tau, torch.float32, "tau"), m, ant0, float(alpha),
+        int(seed), int(iteration), _ptr(tours, torch.int32, "tours"),
+        _ptr(lengths, torch.int64, "lengths"), _ptr(slots, torch.uint8, "slots"),
+        _ptr(step_prob, torch.float32, "step_prob"), _ptr(ws, torch.uint8, "ws"), ws.numel(),
+        _stream(stream)))
+
+
+def aco_update_pheromone(n, k, nn, rev, m, tours, slots, lengths, rho, deposit_shift, tau, ws,
+                         stream=None):
+    torch = _t()
+    _check(lib().aco_update_pheromone(
+        n, k, _ptr(nn, torch.int32, "nn"), _ptr(rev, torch.int8, "rev"), m,
+        _ptr(tours, torch.int32, "tours"), _ptr(slots, torch.uint8, "slots"),
+        _ptr(lengths, torch.int64, "lengths"), float(rho), int(deposit_shift),
+        _ptr(tau, torch.float32, "tau"), _ptr(ws, torch.uint8, "ws"), ws.numel(), _stream(stream)))
+
+
+def aco_track_best(n, m, tours, lengths, best_len, best_tour, iter_best=None, stream=None):
+    torch = _t()
+    _check(lib().aco_track_best(
+        n, m, _ptr(tours, torch.int32, "tours"), _ptr(lengths, torch.int64, "lengths"),
+        _ptr(best_len, torch.int64, "best_len"), _ptr(best_tour, torch.int32, "best_tour"),
+        _ptr(iter_best, torch.int64, "iter_best"), _stream(stream)))
+
+
+def aco_run(xy, n, params: AcoParams, best_tour, best_len, iter_best, tau_out, ws, stream=None):
+    torch = _t()
+    _check(lib().aco_run(
+        _ptr(xy, torch.int32, "xy"), n, C.byref(params), _ptr(best_tour, torch.int32, "best_tour"),
+        _ptr(best_len, torch.int64, "best_len"), _ptr(iter_best, torch.int64, "iter_best"),
+        _ptr(tau_out, torch.float32, "tau_out"), _ptr(ws, torch.uint8, "ws"), ws.numel(),
+        _stream(stream)))
+
+
+# ------------------------------------------------------------ convenience holder
+@dataclass
+class Colony:
+    """Device buffers of one instance plus the calls of one ACO run.
+
+    xy: int32 [n, 2] coordinates (host numpy or GPU tensor)."""
+    xy: object
+    k: int
+    m: int
+    alpha: float = 1.0
+    beta: float = 2.0
+    rho: float = 0.1
+    seed: int = 1
+    deposit_shift: int = 32
+    eta: object = None          # optional learned heuristic score, float32 [n, k] on GPU
+    want_prob: bool = False
+    device: str = "cuda"
+
+    def __post_init__(self):
+        torch = _t()
+        xy = torch.as_tensor(self.xy, dtype=torch.int32)
+        self.xy = xy.to(self.device).contiguous()
+        n, k, m, dev = self.xy.shape[0], self.k, self.m, self.device
+        self.n = n
+        self.nn = torch.empty((n, k), dtype=torch.int32, device=dev)
+        self.nnd = torch.empty((n, k), dtype=torch.int32, device=dev)
+        self.rev = torch.empty((n, k), dtype=torch.int8, device=dev)
+        self.eta_b = torch.empty((n, k), dtype=torch.float32, device=dev)
+        self.grid = torch.empty(aco_grid_bytes(n), dtype=torch.uint8, device=dev)
+        self.tau = torch.empty((n, k), dtype=torch.float32, device=dev)
+        self.nn_tour = torch.empty(n, dtype=torch.int32, device=dev)
+        self.cws = torch.empty(aco_construct_workspace_bytes(n, k), dtype=torch.uint8, device=dev)
+        self.uws = torch.empty(aco_update_workspace_bytes(n, k, m), dtype=torch.uint8, device=dev)
+        self.tours = torch.empty((m, n), dtype=torch.int32, device=dev)
+        self.lengths = torch.empty(m, dtype=torch.int64, device=dev)
+        self.slots = torch.empty((m, n), dtype=torch.uint8, device=dev)
+        self.step_prob = (torch.empty((m, n), dtype=torch.float32, device=dev)
+                          if self.want_prob else None)
+        self.best_tour = torch.empty(n, dtype=torch.int32, device=dev)
+        self.best_len = torch.empty(1, dtype=torch.int64, device=dev)
+        self.tau0 = None
+        self.L_nn = None
+
+    def build_candidates(self, stream=None):
+        aco_build_candidates(self.xy, self.n, self.k, self.beta, self.eta, self.nn, self.nnd,
+                             self.rev, self.eta_b, self.grid, stream)
+
+    def init_pheromone(self, stream=None):
+        self.tau0, self.L_nn = aco_init_pheromone(self.xy, self.n, self.k, self.nn, self.nnd,
+                                                  self.grid, self.nn_tour, self.tau, stream)
+        self.best_tour.copy_(self.nn_tour)
+        self.best_len.fill_(self.L_nn)
+
+    def setup(self, stream=None):
+        self.build_candidates(stream)
+        self.init_pheromone(stream)
+
+    def construct(self, iteration, stream=None, m=None, ant0=0):
+        m = self.m if m is None else m
+        aco_construct_tours(self.xy, self.n, self.k, self.nn, self.nnd, self.eta_b, self.grid,
+                            self.tau, m, ant0, self.alpha, self.seed, iteration, self.tours,
+                            self.lengths, self.slots, self.step_prob, self.cws, stream)
+
+    def track_best(self, iter_best=None, stream=None):
+        aco_track_best(self.n, self.m, self.tours, self.lengths, self.best_len, self.best_tour,
+                       iter_best, stream)
+
+    def update(self, stream=None, use_slots=True):
+        aco_update_pheromone(self.n, self.k, self.nn, self.rev, self.m, self.tours,
+                             self.slots if use_slots else None, self.lengths, self.rho,
+                             self.deposit_shift, self.tau, self.uws, stream)
+
+    def iterate(self, iteration, iter_best=None, stream=None):
+        """One pass of the hot path: construction, best tracking, update."""
+        self.construct(iteration, stream)
+        self.track_best(iter_best, stream)
+        self.update(stream)

@@ -1,0 +1,204 @@
+// Pheromone update (Section 2, Eq. 2-4) and best-tour tracking.
+//
+// Deposits are accumulated in int64 fixed point (q_a = floor(2^shift / L_a)
+// per ant, i.e. 1/C^a with `shift` fraction bits) by integer atomics, so the
+// sum is independent of the order in which ants and edges arrive; the merge
+// then applies evaporation and the deposit with exactly two FP32 roundings.
+#include <cmath>
+
+#include "common.hpp"
+#include "device.hpp"
+
+namespace aco {
+
+__global__ void k_quanta(const int64_t *__restrict__ lengths, int32_t m, int32_t shift,
+                         int64_t *__restrict__ q)
+{
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= m) return;
+    const int64_t L = lengths[a];
+    q[a] = L > 0 ? ((int64_t)1 << shift) / L : 0;
+}
+
+__global__ void k_zero_i64(int64_t *p, int64_t count)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+__device__ __forceinline__ int find_slot(const int32_t *__restrict__ nn, int64_t row, int k,
+                                         int32_t city)
+{
+    for (int r = 0; r < k; ++r)
+        if (nn[row + r] == city) return r;
+    return -1;
+}
+
+// One thread per tour edge (tour[t], tour[t+1 mod n]) of every ant.  The slot
+// of the forward direction comes from the construction record when given
+// (255 = the move was a fallback, so the city is not a candidate); the reverse
+// slot from rev[] or, for edges outside the forward list, a scan of the row.
+__global__ void k_deposit(const int32_t *__restrict__ nn, const int8_t *__restrict__ rev,
+                          int32_t n, int32_t k, int32_t m, const int32_t *__restrict__ tours,
+                          const uint8_t *__restrict__ slots, const int64_t *__restrict__ q,
+                          unsigned long long *__restrict__ acc)
+{
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= (int64_t)m * n) return;
+    const int32_t a = (int32_t)(e / n);
+    const int32_t t = (int32_t)(e - (int64_t)a * n);
+    const int64_t base = (int64_t)a * n;
+    const int32_t i = tours[base + t];
+    const int32_t j = tours[base + (t + 1 == n ? 0 : t + 1)];
+    if (i < 0 || i >= n || j < 0 || j >= n) return;
+    const unsigned long long qa = (unsigned long long)q[a];
+    const int64_t ri = (int64_t)i * k, rj = (int64_t)j * k;
+    int r;
+    if (slots && t + 1 < n) {
+        const uint32_t s = slots[base + t + 1];
+        r = (s < (uint32_t)k && nn[ri + s] == j) ? (int)s : -1;
+        if (s != kNoSlot && r < 0) r = find_slot(nn, ri, k, j);   // defensive
+    } else {
+        r = find_slot(nn, ri, k, j);
+    }
+    int r2;
+    if (r >= 0) {
+        atomicAdd(&acc[ri + r], qa);
+        r2 = rev[ri + r];
+    } else {
+        r2 = find_slot(nn, rj, k, i);
+    }
+    if (r2 >= 0 && r2 < k) atomicAdd(&acc[rj + r2], qa);
+}
+
+// tau = fl32(fl32(tau * f) + fl32(fl32(acc) * 2^-shift)); both products are
+// exact or singly rounded, no fused multiply-add.
+__global__ void k_merge(float *__restrict__ tau, const int64_t *__restrict__ acc, int64_t count,
+                        float f, float scale)
+{
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const float evap = __fmul_rn(tau[e], f);
+        const float dep = __fmul_rn((float)acc[e], scale);
+        tau[e] = __fadd_rn(evap, dep);
+    }
+}
+
+// ---------------------------------------------------------------- best tour
+
+__device__ __forceinline__ int64_t wave_min_i64(int64_t v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const int64_t o = __shfl_xor(v, off);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+// Block-wide minimum (blockDim.x a multiple of 64, at most 1024).
+__device__ __forceinline__ int64_t block_min_i64(int64_t v, int64_t *red)
+{
+    v = wave_min_i64(v);
+    if (lane_id() == 0) red[threadIdx.x / kWave] = v;
+    __syncthreads();
+    int64_t r = INT64_MAX;
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) r = red[w] < r ? red[w] : r;
+    __syncthreads();
+    return r;
+}
+
+// Iteration best: the smallest length, lowest ant on ties.
+__device__ __forceinline__ int32_t best_ant(const int64_t *lengths, int32_t m)
+{
+    __shared__ int64_t red[1024 / kWave];
+    int64_t lmin = INT64_MAX;
+    for (int a = threadIdx.x; a < m; a += blockDim.x) lmin = lengths[a] < lmin ? lengths[a] : lmin;
+    lmin = block_min_i64(lmin, red);
+    int64_t amin = INT64_MAX;
+    for (int a = threadIdx.x; a < m; a += blockDim.x)
+        if (lengths[a] == lmin && a < amin) amin = a;
+    return (int32_t)block_min_i64(amin, red);
+}
+
+// Every block finds the iteration best and copies its share of that tour if
+// it beats the best so far (best_len is only read here).
+__global__ __launch_bounds__(256) void k_best_copy(const int32_t *__restrict__ tours,
+                                                   const int64_t *__restrict__ lengths, int32_t n,
+                                                   int32_t m, const int64_t *best_len,
+                                                   int32_t *best_tour)
+{
+    const int32_t a = best_ant(lengths, m);
+    if (lengths[a] >= *best_len) return;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x)
+        best_tour[t] = tours[(int64_t)a * n + t];
+}
+
+__global__ __launch_bounds__(256) void k_best_finish(const int64_t *__restrict__ lengths,
+                                                     int32_t m, int64_t *best_len,
+                                                     int64_t *iter_best)
+{
+    const int32_t a = best_ant(lengths, m);
+    if (threadIdx.x == 0) {
+        const int64_t L = lengths[a];
+        if (iter_best) *iter_best = L;
+        if (L < *best_len) *best_len = L;
+    }
+}
+
+}  // namespace aco
+
+using namespace aco;
+
+extern "C" size_t aco_update_workspace_bytes(int32_t n, int32_t k, int32_t m)
+{
+    if (n < 1 || k < 1 || m < 1) return 0;
+    return (size_t)n * (size_t)k * 8 + (((size_t)m * 8 + 255) & ~(size_t)255);
+}
+
+extern "C" int aco_update_pheromone(int32_t n, int32_t k, const int32_t *nn, const int8_t *rev,
+                                    int32_t m, const int32_t *tours, const uint8_t *slots,
+                                    const int64_t *lengths, double rho, int32_t deposit_shift,
+                                    float *tau, void *ws, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    ACO_REQUIRE(n >= 3 && n <= (1 << 27), "n = %d out of range [3, 2^27]", n);
+    ACO_REQUIRE(k >= 1 && k <= ACO_MAX_K && k <= n - 1, "k = %d out of range", k);
+    ACO_REQUIRE(m >= 1 && m <= (1 << 20), "m = %d out of range [1, 2^20]", m);
+    ACO_REQUIRE(rho > 0.0 && rho <= 1.0, "rho must lie in (0, 1]");
+    ACO_REQUIRE(deposit_shift >= 0 && deposit_shift <= 62, "deposit_shift out of [0, 62]");
+    ACO_REQUIRE(nn && rev && tours && lengths && tau && ws, "NULL array argument");
+    const size_t need = aco_update_workspace_bytes(n, k, m);
+    if (ws_bytes < need)
+        return fail(ACO_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    hipStream_t st = as_stream(stream);
+    const int64_t nk = (int64_t)n * k;
+    int64_t *acc = (int64_t *)ws;
+    int64_t *q = (int64_t *)((char *)ws + (size_t)nk * 8);
+    k_zero_i64<<<std::min(4096u, blocks_for(nk, 256)), 256, 0, st>>>(acc, nk);
+    k_quanta<<<blocks_for(m, 256), 256, 0, st>>>(lengths, m, deposit_shift, q);
+    k_deposit<<<blocks_for((int64_t)m * n, 256), 256, 0, st>>>(
+        nn, rev, n, k, m, tours, slots, q, (unsigned long long *)acc);
+    const float f = (float)(1.0 - rho);
+    const float scale = std::ldexp(1.0f, -deposit_shift);
+    k_merge<<<std::min(8192u, blocks_for(nk, 256)), 256, 0, st>>>(tau, acc, nk, f, scale);
+    ACO_LAUNCH_CHECK("update kernels");
+    return ACO_OK;
+}
+
+extern "C" int aco_track_best(int32_t n, int32_t m, const int32_t *tours, const int64_t *lengths,
+                              int64_t *best_len, int32_t *best_tour, int64_t *iter_best,
+                              void *stream)
+{
+    clear_error();
+    ACO_REQUIRE(n >= 3 && m >= 1 && m <= (1 << 20), "bad sizes n = %d, m = %d", n, m);
+    ACO_REQUIRE(tours && lengths && best_len && best_tour, "NULL array argument");
+    hipStream_t st = as_stream(stream);
+    k_best_copy<<<std::min(1024u, blocks_for(n, 256)), 256, 0, st>>>(tours, lengths, n, m,
+                                                                    best_len, best_tour);
+    k_best_finish<<<1, 256, 0, st>>>(lengths, m, best_len, iter_best);
+    ACO_LAUNCH_CHECK("best tracking");
+    return ACO_OK;
+}

@@ -49,3 +49,11 @@ def test_rev(orc):
             j = nn[i, r]
             hit = np.nonzero(nn[j] == i)[0]
             assert rv[i, r] == (hit[0] if len(hit) else -1)
+
+
+def test_knn_threaded_equals_serial(orc):
+    xy = instances.clustered_coords(3000, 5, clusters=7, sigma=2e4)
+    a = orc.knn_rows(xy, 12)
+    b = orc.knn_rows(xy, 12, threads=5)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
