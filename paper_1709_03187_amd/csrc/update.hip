@@ -36,9 +36,9 @@ __device__ __forceinline__ int find_slot(const int32_t *__restrict__ nn, int64_t
 }
 
 // One thread per tour edge (tour[t], tour[t+1 mod n]) of every ant.  The slot
-// of the forward direction comes from the construction record when given
-// (255 = the move was a fallback, so the city is not a candidate); the reverse
-// slot from rev[] or, for edges outside the forward list, a scan of the row.
+// of the forward direction comes from the construction record when it names
+// the edge; the reverse slot from rev[] or, for edges outside the forward
+// list, a scan of the other row.
 __global__ void k_deposit(const int32_t *__restrict__ nn, const int8_t *__restrict__ rev,
                           int32_t n, int32_t k, int32_t m, const int32_t *__restrict__ tours,
                           const uint8_t *__restrict__ slots, const int64_t *__restrict__ q,
@@ -54,14 +54,15 @@ __global__ void k_deposit(const int32_t *__restrict__ nn, const int8_t *__restri
     if (i < 0 || i >= n || j < 0 || j >= n) return;
     const unsigned long long qa = (unsigned long long)q[a];
     const int64_t ri = (int64_t)i * k, rj = (int64_t)j * k;
-    int r;
+    // A fallback move (slot 255) can still end on a candidate city: that happens
+    // when every unvisited candidate has zero weight.  Such edges are located
+    // by scanning the row, as are edges without a construction record.
+    int r = -1;
     if (slots && t + 1 < n) {
         const uint32_t s = slots[base + t + 1];
-        r = (s < (uint32_t)k && nn[ri + s] == j) ? (int)s : -1;
-        if (s != kNoSlot && r < 0) r = find_slot(nn, ri, k, j);   // defensive
-    } else {
-        r = find_slot(nn, ri, k, j);
+        if (s < (uint32_t)k && nn[ri + s] == j) r = (int)s;
     }
+    if (r < 0) r = find_slot(nn, ri, k, j);
     int r2;
     if (r >= 0) {
         atomicAdd(&acc[ri + r], qa);
