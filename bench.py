@@ -1,0 +1,202 @@
+"""Benchmark of the ACO hot path on one MI355X.
+
+Workload: n = 200,000 clustered cities (100 Gaussian clusters, sigma = 1e4,
+integer coordinates), m = 1,024 ants, k = 16 candidates, alpha = 1, beta = 2,
+rho = 0.1, Philox seed 3.  A step is one ACO iteration: tour construction of
+all ants, best tracking, and the pheromone update.  Candidate lists, grid and
+NN-tour initialisation run once before the timed region.
+
+Prints one JSON line.  `value` = ant-steps per second over whole iterations,
+m * (n - 1) ant-steps per iteration.  `roofline` prices the construction
+kernel by its algorithmic bytes per ant-step.  `cpu_baseline` times the CPU
+oracle (threads over ants) on a fixed sample of ants of the same workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "c3"
+
+
+def construct_bytes_per_step(k: int) -> int:
+    """Algorithmic bytes of one ant-step of construction: the candidate row
+    {city int32, weight fp32} x k, the tour entry (int32), the slot record
+    (uint8) and the chosen edge's distance (int32)."""
+    return 8 * k + 4 + 1 + 4
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(xy, cfg, tau0_gpu, threads, ants_per_thread=4):
+    """Oracle construction of a fixed sample of ants (iteration 0) on the host."""
+    import oracle as orc
+    n, k = len(xy), cfg["k"]
+    t0 = time.time()
+    nn, nnd = orc.knn_rows(xy, k, threads=threads)
+    t_knn = time.time() - t0
+    L_nn = orc.nn_tour(xy, nn, nnd)[1]
+    tau = np.full((n, k), orc.tau0(n, L_nn), np.float32)
+    count = ants_per_thread * threads
+    t0 = time.time()
+    res = orc.construct(xy, nn, nnd, tau, cfg["alpha"], cfg["beta"], cfg["seed"], 0,
+                        np.arange(count), threads=threads)
+    dt = time.time() - t0
+    return dict(value=count * (n - 1) / dt, unit="ant-steps/s", cores=threads, kind="oracle",
+                sample=f"{count} ants of iteration 0 at n={n} (FP64, O(n) fallback), "
+                       f"{dt:.1f} s; candidate lists took {t_knn:.1f} s and are not counted",
+                L_nn=L_nn, tau0_matches_gpu=bool(orc.tau0(n, L_nn) == np.float32(tau0_gpu)),
+                sample_best_len=int(res["lengths"].min()),
+                fallback_share=float(res["fallbacks"].sum() / (count * (n - 1))))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=6)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the colony would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1709_03187_amd as aco
+    from paper_1709_03187_amd import instances
+
+    cfg = instances.CONFIGS[WORKLOAD]
+    n, m, k = cfg["n"], cfg["m"], cfg["k"]
+    xy = instances.make_coords(WORKLOAD)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log(f"[bench] {WORKLOAD}: n={n} m={m} k={k}")
+
+    # calibration copy for the HBM traffic counters (known size, 256 MiB each way)
+    src = torch.empty(64 * 2**20, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+    col = aco.Colony(xy=xy, k=k, m=m, alpha=cfg["alpha"], beta=cfg["beta"], rho=cfg["rho"],
+                     seed=cfg["seed"], device="cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.time()
+    col.build_candidates()
+    torch.cuda.synchronize()
+    t_cand = time.time() - t0
+    t0 = time.time()
+    col.init_pheromone()
+    torch.cuda.synchronize()
+    t_init = time.time() - t0
+    log(f"[bench] candidates {t_cand*1e3:.1f} ms, NN-tour init {t_init*1e3:.1f} ms, "
+        f"L_nn={col.L_nn}")
+
+    iters = args.warmup + args.steps
+    iter_best = torch.empty(iters, dtype=torch.int64, device=dev)
+    for it in range(args.warmup):
+        col.iterate(it, iter_best[it:it + 1])
+        torch.cuda.synchronize()
+        log(f"[bench] warmup iteration {it} done")
+
+    stream = torch.cuda.current_stream()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    wall0 = time.time()
+    for s in range(args.steps):
+        it = args.warmup + s
+        e = ev[s]
+        e[0].record(stream)
+        col.construct(it)
+        e[1].record(stream)
+        col.track_best(iter_best[it:it + 1])
+        e[2].record(stream)
+        col.update()
+        e[3].record(stream)
+    torch.cuda.synchronize()
+    wall = time.time() - wall0
+    t_con = np.array([ev[s][0].elapsed_time(ev[s][1]) for s in range(args.steps)])
+    t_best = np.array([ev[s][1].elapsed_time(ev[s][2]) for s in range(args.steps)])
+    t_upd = np.array([ev[s][2].elapsed_time(ev[s][3]) for s in range(args.steps)])
+    t_step = np.array([ev[s][0].elapsed_time(ev[s][3]) for s in range(args.steps)])
+    for s in range(args.steps):
+        log(f"[bench] step {s}: construct {t_con[s]:.2f} ms, best {t_best[s]:.3f} ms, "
+            f"update {t_upd[s]:.2f} ms")
+
+    steps_per_iter = m * (n - 1)
+    ms_per_step = float(t_step.mean())
+    value = steps_per_iter / (ms_per_step * 1e-3)
+    bps = construct_bytes_per_step(k)
+    achieved = steps_per_iter * bps / (t_con.mean() * 1e-3) / 1e9
+    ib = iter_best.cpu().numpy()
+    best_len = int(col.best_len.item())
+
+    out = {
+        "metric": "ant construction steps/sec at n=200K",
+        "value": value,
+        "unit": "ant-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "n=200,000 clustered cities (100 Gaussian clusters, sigma=1e4, "
+                               "integer coords), m=1,024 ants, k=16, alpha=1, beta=2, rho=0.1, "
+                               "int64 fixed-point deposit (2^-32), Philox seed 3",
+                   "n": n, "m": m, "k": k, "iterations_timed": args.steps,
+                   "parallelism": "one ant per wavefront"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_construct (with its k_choice_info prologue)",
+                     "bytes_per_ant_step": bps},
+        "construct_ms": float(t_con.mean()),
+        "update_ms": float(t_upd.mean()),
+        "best_ms": float(t_best.mean()),
+        "construct_ant_steps_per_s": steps_per_iter / (t_con.mean() * 1e-3),
+        "setup_ms": {"candidates": t_cand * 1e3, "nn_tour_init": t_init * 1e3},
+        "wall_s_timed": wall,
+        "L_nn": col.L_nn,
+        "iter_best": [int(v) for v in ib],
+        "best_len": best_len,
+    }
+    if not args.no_cpu_baseline:
+        threads = args.cpu_threads or max(1, min(16, os.cpu_count() or 1))
+        log(f"[bench] cpu baseline with {threads} threads")
+        cb = cpu_baseline(xy, cfg, col.tau0, threads)
+        out["cpu_baseline"] = {kk: cb[kk] for kk in ("value", "unit", "cores", "kind", "sample")}
+        # equal wall time: the oracle cannot finish one iteration in the GPU's time, so its
+        # best so far is its NN tour
+        gpu_time = t_cand + t_init + wall
+        out["equal_time"] = {"gpu_seconds": gpu_time, "gpu_best": best_len,
+                             "oracle_best": cb["L_nn"],
+                             "gap": (best_len - cb["L_nn"]) / cb["L_nn"],
+                             "oracle_ant_steps_in_that_time": cb["value"] * gpu_time}
+        out["cpu_baseline_extra"] = {"tau0_matches_gpu": cb["tau0_matches_gpu"],
+                                     "fallback_share": cb["fallback_share"],
+                                     "sample_best_len": cb["sample_best_len"]}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
