@@ -140,9 +140,10 @@ int aco_construct_tours(const int32_t *xy, int32_t n, int32_t k, const int32_t *
  * outside the candidate lists carry no pheromone.  Sums are exact in int64,
  * and the merge is tau = fl32(tau' + fl32(acc) * 2^-deposit_shift).
  *
- *   tours int32 [m][n] (any permutations), slots uint8 [m][n] from
- *   aco_construct_tours or NULL (then every edge is located by scanning the
- *   candidate rows), lengths int64 [m] > 0, 0 < rho <= 1,
+ *   tours int32 [m][n] (any permutations), slots uint8 [m][n]: the record
+ *   aco_construct_tours wrote for exactly these tours (trusted, only range
+ *   checked), or NULL (then every edge is located by scanning the candidate
+ *   rows), lengths int64 [m] > 0, 0 < rho <= 1,
  *   0 <= deposit_shift <= 62 (the caller keeps m * 2^shift / min L < 2^63),
  *   tau float [n][k] (in/out), ws: aco_update_workspace_bytes(n, k, m) bytes.
  * Errors: INVALID_ARG, WORKSPACE.

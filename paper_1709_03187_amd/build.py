@@ -45,8 +45,11 @@ def build(verbose: bool = False) -> str:
         r = subprocess.run(cmd, capture_output=True, text=True, cwd=bdir)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
-        if verbose and r.stderr.strip():
-            print(r.stderr, file=sys.stderr)
+        # the host pass does not know the packed-FP32 feature flag: harmless, drop it
+        err = "\n".join(line for line in r.stderr.splitlines()
+                        if line.strip() and "packed-fp32-ops' is not a recognized" not in line)
+        if verbose and err:
+            print(err, file=sys.stderr)
         return obj
 
     with ThreadPoolExecutor(max_workers=min(4, os.cpu_count() or 1)) as ex:

@@ -117,29 +117,32 @@ __global__ void k_grid_scatter(const int32_t *__restrict__ xy, GridHdr h, int32_
 // ------------------------------------------------------------------ k-NN build
 
 // One thread per city, cities taken in grid order so that a wave works on
-// neighbouring cities.  Each thread walks rings of cells around its city and
-// keeps the k smallest keys (d, j) sorted in LDS (interleaved by thread to
-// avoid bank conflicts); it stops once every point outside the searched block
-// is farther than the current k-th distance.
+// neighbouring cities.  Each thread scans square blocks of cells of growing
+// radius (1, 3, 7, ...) around its city and keeps the k smallest keys (d, j)
+// sorted in LDS (interleaved by thread to avoid bank conflicts); it stops once
+// every point outside the searched block is farther than the k-th distance.
 constexpr int kKnnThreads = 64;
 
-__global__ __launch_bounds__(kKnnThreads) void k_knn(const void *grid, int32_t k, int32_t *nn,
+__global__ __launch_bounds__(kKnnThreads) void k_knn(void *grid, int32_t k, int32_t *nn,
                                                       int32_t *nnd)
 {
-    extern __shared__ uint64_t lists[];   // [k][kKnnThreads]
+    extern __shared__ uint64_t lists[];   // [kx][kKnnThreads]
     const GridView g = grid_view(grid);
     const GridHdr &h = g.h;
+    const int kx = h.kx;                  // k <= kx: the candidate list is the table's prefix
+    int32_t *ext = (int32_t *)g.ext;
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= h.n) return;
     uint64_t *L = lists + threadIdx.x;
     const int4 me = g.pts[p];
     const int gx = cell_x(h, me.x), gy = cell_y(h, me.y);
     int cnt = 0;
-    for (int r = 0;; ++r) {
-        const int nseg = ring_segments(r);
-        for (int s = 0; s < nseg; ++s) {
+    int rin = -1;
+    for (int r = 1;; rin = r, r = 2 * r + 1) {
+        const int nslots = 2 * (2 * r + 1);
+        for (int s = 0; s < nslots; ++s) {
             int row, xa, xb;
-            if (!ring_segment(h, gx, gy, r, s, row, xa, xb)) continue;
+            if (!block_slot(h, gx, gy, rin, r, s, row, xa, xb)) continue;
             const int a = g.cell_start[(int64_t)row * h.gw + xa];
             const int b = g.cell_start[(int64_t)row * h.gw + xb + 1];
             for (int q = a; q < b; ++q) {
@@ -148,8 +151,8 @@ __global__ __launch_bounds__(kKnnThreads) void k_knn(const void *grid, int32_t k
                 const uint64_t key =
                     ((uint64_t)(uint32_t)nint_sqrt(sq_dist(me.x, me.y, pt.x, pt.y)) << 32) |
                     (uint32_t)pt.z;
-                if (cnt == k && key >= L[(int64_t)(k - 1) * kKnnThreads]) continue;
-                int pos = cnt < k ? cnt++ : k - 1;
+                if (cnt == kx && key >= L[(int64_t)(kx - 1) * kKnnThreads]) continue;
+                int pos = cnt < kx ? cnt++ : kx - 1;
                 while (pos > 0 && L[(int64_t)(pos - 1) * kKnnThreads] > key) {
                     L[(int64_t)pos * kKnnThreads] = L[(int64_t)(pos - 1) * kKnnThreads];
                     --pos;
@@ -159,13 +162,16 @@ __global__ __launch_bounds__(kKnnThreads) void k_knn(const void *grid, int32_t k
         }
         int64_t bound;
         if (!outside_bound(h, me.x, me.y, gx, gy, r, bound)) break;
-        if (cnt == k && bound > (int64_t)(L[(int64_t)(k - 1) * kKnnThreads] >> 32)) break;
+        if (cnt == kx && bound > (int64_t)(L[(int64_t)(kx - 1) * kKnnThreads] >> 32)) break;
     }
-    const int64_t row = (int64_t)me.z * k;
-    for (int r = 0; r < k; ++r) {
+    const int64_t row = (int64_t)me.z * k, xrow = (int64_t)me.z * kx;
+    for (int r = 0; r < kx; ++r) {
         const uint64_t key = L[(int64_t)r * kKnnThreads];
-        nn[row + r] = (int32_t)(uint32_t)key;
-        nnd[row + r] = (int32_t)(key >> 32);
+        ext[xrow + r] = (int32_t)(uint32_t)key;
+        if (r < k) {
+            nn[row + r] = (int32_t)(uint32_t)key;
+            nnd[row + r] = (int32_t)(key >> 32);
+        }
     }
 }
 
@@ -239,10 +245,10 @@ __global__ __launch_bounds__(kWave) void k_nn_tour(const int32_t *__restrict__ x
             jn = read_lane_i32(j, f);
             dn = read_lane_i32(d, f);
         } else {
-            const int32_t cx = xy[2 * (int64_t)c], cy = xy[2 * (int64_t)c + 1];
-            const uint64_t key = wave_nearest_unvisited(g, cx, cy, visited);
-            jn = (int32_t)(uint32_t)key;
-            dn = (int32_t)(key >> 32);
+            jn = fallback_city(g, xy, c, visited);
+            jn = ((uint32_t)jn < (uint32_t)n) ? jn : 0;   // range guard (see construct.hip)
+            dn = nint_sqrt(sq_dist(xy[2 * (int64_t)c], xy[2 * (int64_t)c + 1],
+                                   xy[2 * (int64_t)jn], xy[2 * (int64_t)jn + 1]));
         }
         jn = ((uint32_t)jn < (uint32_t)n) ? jn : 0;   // range guard (see construct.hip)
         if (lane == 0) atomicOr(&vis[jn >> 5], 1u << (jn & 31));
@@ -311,6 +317,7 @@ int build_grid(const int32_t *xy, int32_t n, void *grid, size_t grid_bytes, hipS
     h.ncell = h.gw * h.gh;
     h.n = n;
     h.cap = (int32_t)GridLayout::cap_for(n);
+    h.kx = ext_width(n);
     if ((int64_t)h.gw * h.gh + 1 > h.cap)
         return fail(ACO_ERR_HIP, "grid sizing error (%d x %d cells)", h.gw, h.gh);
     int32_t *cell_start = (int32_t *)(gb + lay.cell_start);
@@ -348,7 +355,7 @@ extern "C" int aco_build_candidates(const int32_t *xy, int32_t n, int32_t k, dou
     hipStream_t st = as_stream(stream);
     int rc = build_grid(xy, n, grid, grid_bytes, st);
     if (rc != ACO_OK) return rc;
-    const size_t lds = (size_t)k * kKnnThreads * sizeof(uint64_t);
+    const size_t lds = (size_t)ext_width(n) * kKnnThreads * sizeof(uint64_t);
     k_knn<<<blocks_for(n, kKnnThreads), kKnnThreads, lds, st>>>(grid, k, nn, nnd);
     ACO_LAUNCH_CHECK("k_knn");
     const int64_t nk = (int64_t)n * k;

@@ -59,7 +59,6 @@ __global__ void k_choice_info(const int32_t *__restrict__ nn, const float *__res
 struct ConstructArgs {
     const int32_t *xy;
     const CandW *rows;
-    const int32_t *nnd;
     const void *grid;
     int32_t n, k;
     int32_t ant0;
@@ -71,6 +70,14 @@ struct ConstructArgs {
     float *step_prob;
 };
 
+// One ant per wavefront.  Lane r < k holds candidate r of the current city.
+// The critical path of a step is: row load -> visited test (LDS) -> DPP scan
+// -> ballot -> next row address.  (Touching the candidates' rows ahead of time
+// does not help: vector loads complete in order, so the next row load would
+// wait for the slowest of those touches.)
+// KP is the scan width: the smallest power of two >= k (a template parameter
+// so that the per-step code has no branches besides the roulette/fallback).
+template <int KP>
 __global__ __launch_bounds__(kWave) void k_construct(ConstructArgs A)
 {
     extern __shared__ uint32_t vis[];
@@ -78,7 +85,6 @@ __global__ __launch_bounds__(kWave) void k_construct(ConstructArgs A)
     const int32_t n = A.n, k = A.k;
     const int32_t a = blockIdx.x;                 // ant within this launch
     const uint32_t ant = (uint32_t)(A.ant0 + a);  // absolute ant index (Philox counter)
-    const GridView g = grid_view(A.grid);
     const int nwords = (n + 31) >> 5;
     for (int w = lane; w < nwords; w += kWave) vis[w] = 0u;
     __syncthreads();
@@ -87,6 +93,7 @@ __global__ __launch_bounds__(kWave) void k_construct(ConstructArgs A)
     int32_t *tour_out = A.tours + (int64_t)a * n;
     uint8_t *slot_out = A.slots + (int64_t)a * n;
     float *prob_out = A.step_prob ? A.step_prob + (int64_t)a * n : nullptr;
+    const bool want_prob = prob_out != nullptr;
 
     // lane l holds the Philox word of step (base + l)
     uint32_t rnd = colony_draw(A.seed, A.iteration, ant, (uint32_t)lane);
@@ -99,32 +106,23 @@ __global__ __launch_bounds__(kWave) void k_construct(ConstructArgs A)
     uint32_t st_slot = kNoSlot;
     float st_prob = 1.0f;
     int32_t c = start;
-    int64_t L = 0;
-    int kp = 1;
-    while (kp < k) kp <<= 1;
+    const bool active = lane < k;
+    const int lr = active ? lane : k - 1;   // idle lanes re-read a valid element
+    GridView g;
+    bool have_grid = false;
 
     for (int32_t step = 1; step < n; ++step) {
         if ((step & 63) == 0) rnd = colony_draw(A.seed, A.iteration, ant, (uint32_t)(step + lane));
-        const int64_t rb = (int64_t)c * k;
-        int32_t j = 0, d = 0;
-        float wf = 0.0f;
-        if (lane < k) {
-            const CandW e = A.rows[rb + lane];
-            j = e.city;
-            wf = e.w;
-            d = A.nnd[rb + lane];
-        }
-        const bool unv = (lane < k) && !visited(j);
-        const double wv = (unv && wf > 0.0f) ? (double)wf : 0.0;
-        double cum = wv;
-        for (int off = 1; off < kp; off <<= 1) {
-            const double t = __shfl_up(cum, off);
-            if (lane >= off) cum += t;
-        }
+        const CandW e = A.rows[(int64_t)c * k + lr];
+        const int32_t j = e.city;
+        const uint32_t seen = visited(j);          // every lane reads a valid word
+        const bool unv = active && seen == 0u;
+        const double wv = (unv && e.w > 0.0f) ? (double)e.w : 0.0;
+        const double cum = wave_incl_scan_f64(wv, KP);
         const double S = read_lane_f64(cum, k - 1);
-        int32_t jn, dn;
+        int32_t jn;
         uint32_t slot;
-        float prob;
+        float prob = -1.0f;
         if (S > 0.0) {
             const uint32_t x = (uint32_t)read_lane_i32((int32_t)rnd, step & 63);
             const double target = (double)x * 0x1p-32 * S;
@@ -132,16 +130,15 @@ __global__ __launch_bounds__(kWave) void k_construct(ConstructArgs A)
             const int f = hit ? __ffsll((unsigned long long)hit) - 1
                               : 63 - __clzll((long long)__ballot(wv > 0.0));
             jn = read_lane_i32(j, f);
-            dn = read_lane_i32(d, f);
             slot = (uint32_t)f;
-            prob = (float)(read_lane_f64(wv, f) / S);
+            if (want_prob) prob = (float)(read_lane_f64(wv, f) / S);
         } else {
-            const int32_t cx = A.xy[2 * (int64_t)c], cy = A.xy[2 * (int64_t)c + 1];
-            const uint64_t key = wave_nearest_unvisited(g, cx, cy, visited);
-            jn = (int32_t)(uint32_t)key;
-            dn = (int32_t)(key >> 32);
+            if (!have_grid) {
+                g = grid_view(A.grid);
+                have_grid = true;
+            }
+            jn = fallback_city(g, A.xy, c, visited);
             slot = kNoSlot;
-            prob = -1.0f;
         }
         // a city index is always in range here; the clamp only keeps a logic
         // error from turning into an out-of-bounds access (tests see the tour)
@@ -157,16 +154,42 @@ __global__ __launch_bounds__(kWave) void k_construct(ConstructArgs A)
             if (base + lane <= step) {
                 tour_out[base + lane] = st_city;
                 slot_out[base + lane] = (uint8_t)st_slot;
-                if (prob_out) prob_out[base + lane] = st_prob;
+                if (want_prob) prob_out[base + lane] = st_prob;
             }
         }
-        L += dn;
         c = jn;
     }
-    const int64_t s = sq_dist(A.xy[2 * (int64_t)c], A.xy[2 * (int64_t)c + 1],
-                              A.xy[2 * (int64_t)start], A.xy[2 * (int64_t)start + 1]);
-    L += nint_sqrt(s);
-    if (lane == 0) A.lengths[a] = L;
+    if (lane == 0) A.lengths[a] = 0;     // summed by k_tour_length
+}
+
+// Tour lengths: one block of 256 threads per (ant, chunk of 256 tour edges),
+// exact integer distances, one int64 atomic per block.
+constexpr int kLenThreads = 256;
+
+__global__ __launch_bounds__(kLenThreads) void k_tour_length(const int32_t *__restrict__ xy,
+                                                             const int32_t *__restrict__ tours,
+                                                             int32_t n, int32_t chunks,
+                                                             unsigned long long *lengths)
+{
+    __shared__ int64_t part[kLenThreads / kWave];
+    const int32_t a = blockIdx.x / chunks;
+    const int32_t t = (blockIdx.x - a * chunks) * kLenThreads + threadIdx.x;
+    int64_t d = 0;
+    if (t < n) {
+        const int32_t *T = tours + (int64_t)a * n;
+        const int32_t i = T[t], j = T[t + 1 == n ? 0 : t + 1];
+        d = nint_sqrt(sq_dist(xy[2 * (int64_t)i], xy[2 * (int64_t)i + 1], xy[2 * (int64_t)j],
+                              xy[2 * (int64_t)j + 1]));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off);
+    if (lane_id() == 0) part[threadIdx.x / kWave] = d;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t s = 0;
+        for (int w = 0; w < kLenThreads / kWave; ++w) s += part[w];
+        atomicAdd(&lengths[a], (unsigned long long)s);
+    }
 }
 
 }  // namespace aco
@@ -205,12 +228,20 @@ extern "C" int aco_construct_tours(const int32_t *xy, int32_t n, int32_t k, cons
     CandW *rows = (CandW *)ws;
     k_choice_info<<<blocks_for(n, 256), 256, 0, st>>>(nn, tau, eta_b, n, k, alpha, rows);
     ACO_LAUNCH_CHECK("k_choice_info");
+    void (*kern)(ConstructArgs) = k <= 8    ? k_construct<8>
+                                  : k <= 16 ? k_construct<16>
+                                  : k <= 32 ? k_construct<32>
+                                            : k_construct<64>;
     if (lds > 65536)
-        ACO_HIP_CHECK(hipFuncSetAttribute((const void *)k_construct,
+        ACO_HIP_CHECK(hipFuncSetAttribute((const void *)kern,
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    ConstructArgs A{xy, rows, nnd, grid, n, k, ant0, (uint32_t)iteration, seed,
+    ConstructArgs A{xy, rows, grid, n, k, ant0, (uint32_t)iteration, seed,
                     tours, lengths, slots, step_prob};
-    k_construct<<<m, kWave, lds, st>>>(A);
+    kern<<<m, kWave, lds, st>>>(A);
     ACO_LAUNCH_CHECK("k_construct");
+    const int32_t chunks = (n + kLenThreads - 1) / kLenThreads;
+    k_tour_length<<<(unsigned)((int64_t)m * chunks), kLenThreads, 0, st>>>(
+        xy, tours, n, chunks, (unsigned long long *)lengths);
+    ACO_LAUNCH_CHECK("k_tour_length");
     return ACO_OK;
 }

@@ -92,6 +92,32 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v)
     return v;
 }
 
+// DPP move of a 64-bit value (both halves moved by the same pattern); lanes
+// whose source is outside the row, or whose row is masked off, receive 0.
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, Ctrl, RowMask, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), Ctrl, RowMask, 0xF,
+                                               true);
+    return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+// Inclusive prefix sum over lanes 0..width-1 (width a power of two <= 64,
+// wave-uniform) with DPP: row shifts by 1, 2, 4, 8 inside each 16-lane row,
+// then the row broadcasts of lane 15 and lane 31 carry totals across rows.
+__device__ __forceinline__ double wave_incl_scan_f64(double v, int width)
+{
+    if (width > 1) v += dpp_f64<0x111, 0xF>(v);    // row_shr:1
+    if (width > 2) v += dpp_f64<0x112, 0xF>(v);    // row_shr:2
+    if (width > 4) v += dpp_f64<0x114, 0xF>(v);    // row_shr:4
+    if (width > 8) v += dpp_f64<0x118, 0xF>(v);    // row_shr:8
+    if (width > 16) v += dpp_f64<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+    if (width > 32) v += dpp_f64<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
 __device__ __forceinline__ int wave_incl_scan_i32(int v, int lane)
 {
 #pragma unroll
@@ -115,18 +141,27 @@ struct GridHdr {
     int32_t ncell;    // gw * gh
     int32_t n;        // cities
     int32_t cap;      // capacity of cell_start (>= ncell + 1)
+    int32_t kx;       // width of the extended neighbour table
 };
+
+// Extended neighbour table: the kx = min(64, n - 1) nearest cities of every
+// city in (d, index) order.  Its first k columns are the candidate list; the
+// rest lets the fallback find the nearest unvisited city with one row read
+// whenever one of those kx cities is still unvisited.
+constexpr int kExtWidth = 64;
+__host__ __device__ inline int ext_width(int64_t n) { return n - 1 < kExtWidth ? (int)(n - 1) : kExtWidth; }
 
 struct GridView {
     GridHdr h;
     const int32_t *cell_start;   // [ncell + 1]
     const int4 *pts;             // [n] {x, y, city, 0} in cell order
+    const int32_t *ext;          // [n][kx]
 };
 
 // Byte layout of the grid buffer (offsets aligned to 256 bytes).
 struct GridLayout {
     static constexpr size_t kAuxOffset = 128;   // 8-byte scratch slot inside the header block
-    size_t hdr, cell_start, cursor, pts, total;
+    size_t hdr, cell_start, cursor, pts, ext, total;
     static __host__ __device__ size_t align(size_t v) { return (v + 255) & ~(size_t)255; }
     static __host__ __device__ int64_t cap_for(int64_t n) { return 3 * n + 2; }
     __host__ __device__ explicit GridLayout(int64_t n)
@@ -136,7 +171,8 @@ struct GridLayout {
         cell_start = align(sizeof(GridHdr));
         cursor = align(cell_start + (size_t)(cap + 1) * 4);
         pts = align(cursor + (size_t)cap * 4);
-        total = align(pts + (size_t)n * 16);
+        ext = align(pts + (size_t)n * 16);
+        total = align(ext + (size_t)n * ext_width(n) * 4);
     }
 };
 
@@ -148,16 +184,19 @@ __device__ __forceinline__ GridView grid_view(const void *grid)
     const GridLayout L(g.h.n);
     g.cell_start = (const int32_t *)(b + L.cell_start);
     g.pts = (const int4 *)(b + L.pts);
+    g.ext = (const int32_t *)(b + L.ext);
     return g;
 }
 
+// Cell coordinates of a city: offsets from the box corner are below 2^30, so
+// unsigned 32-bit division is exact (and much cheaper than 64-bit).
 __device__ __forceinline__ int cell_x(const GridHdr &h, int32_t x)
 {
-    return (int)(((int64_t)x - h.x0) / h.cell);
+    return (int)((uint32_t)(x - h.x0) / (uint32_t)h.cell);
 }
 __device__ __forceinline__ int cell_y(const GridHdr &h, int32_t y)
 {
-    return (int)(((int64_t)y - h.y0) / h.cell);
+    return (int)((uint32_t)(y - h.y0) / (uint32_t)h.cell);
 }
 
 // Smallest distance from (cx, cy) to any integer point outside the block of
@@ -192,35 +231,80 @@ __device__ __forceinline__ bool outside_bound(const GridHdr &h, int32_t cx, int3
     return any;
 }
 
-// Segment s of ring r around (gx, gy) as a range of cells in one grid row:
-// s = 0, 1 are the bottom/top rows of the ring; s >= 2 the single side cells.
-// Returns false if the segment lies outside the grid.
-__device__ __forceinline__ bool ring_segment(const GridHdr &h, int gx, int gy, int r, int s,
-                                             int &row, int &xa, int &xb)
+// Inclusive prefix sum of an int over all 64 lanes with DPP row shifts and
+// row broadcasts (no LDS round trips).
+__device__ __forceinline__ int wave_incl_scan_i32_dpp(int v)
 {
-    if (r == 0) {
-        row = gy;
-        xa = xb = gx;
-    } else if (s < 2) {
-        row = (s == 0) ? gy - r : gy + r;
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, true);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, true);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, true);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, true);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, true);   // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, true);   // row_bcast:31
+    return v;
+}
+
+// Minimum of a 64-bit key over the wave; the result is valid in lane 63.
+// Lanes whose DPP source is invalid (or whose row is masked) keep their own
+// value, so the neutral element never has to be materialised.
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ uint64_t dpp_min_step_u64(uint64_t v)
+{
+    const int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
+    const uint32_t olo = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, Ctrl, RowMask, 0xF, false);
+    const uint32_t ohi = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, Ctrl, RowMask, 0xF, false);
+    const uint64_t o = ((uint64_t)ohi << 32) | olo;
+    return o < v ? o : v;
+}
+
+__device__ __forceinline__ uint64_t wave_min_u64_dpp(uint64_t v)
+{
+    v = dpp_min_step_u64<0x111, 0xF>(v);
+    v = dpp_min_step_u64<0x112, 0xF>(v);
+    v = dpp_min_step_u64<0x114, 0xF>(v);
+    v = dpp_min_step_u64<0x118, 0xF>(v);
+    v = dpp_min_step_u64<0x142, 0xA>(v);
+    v = dpp_min_step_u64<0x143, 0xC>(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Slot s of the region searched when the block radius grows from rin to r
+// (rin = -1 for the first pass): row y = gy - r + (s >> 1); rows farther than
+// rin from gy contribute their full span [gx - r, gx + r] (side 0), rows of
+// the inner block their left and right remainders (side 0 / side 1).  The
+// cells of one grid row are consecutive, so each slot is one contiguous range
+// of `pts`.  Returns false for an empty or off-grid slot.
+__device__ __forceinline__ bool block_slot(const GridHdr &h, int gx, int gy, int rin, int r, int s,
+                                           int &row, int &xa, int &xb)
+{
+    row = gy - r + (s >> 1);
+    const int side = s & 1;
+    const int dy = row > gy ? row - gy : gy - row;
+    if (dy > rin) {
+        if (side) return false;
         xa = gx - r;
         xb = gx + r;
+    } else if (side == 0) {
+        xa = gx - r;
+        xb = gx - rin - 1;
     } else {
-        const int q = s - 2;
-        row = gy - r + 1 + (q >> 1);
-        xa = xb = (q & 1) ? gx + r : gx - r;
+        xa = gx + rin + 1;
+        xb = gx + r;
     }
     xa = xa < 0 ? 0 : xa;
     xb = xb > h.gw - 1 ? h.gw - 1 : xb;
     return row >= 0 && row < h.gh && xa <= xb;
 }
 
-__device__ __forceinline__ int ring_segments(int r) { return r == 0 ? 1 : 4 * r; }
-
-// Nearest unvisited city to (cx, cy) by key (d, city), searched ring by ring
-// on the grid by the whole wave.  `visited(city)` tests the ant's bitmask.
-// Rings stop once every point outside the searched block is provably farther
-// than the best distance found (bound > d_best), so the result is exact.
+// Nearest unvisited city to (cx, cy) by key (d, city), searched by the whole
+// wave over square blocks of cells: radius 1 first, then one more ring per
+// pass.  Each pass reads the new cells as contiguous row ranges of `pts`, one
+// city per lane, and keeps a lane-local minimum (the distance is only rounded
+// for cities that can beat it); one wave reduction per pass.  The search stops
+// once every city outside the searched block is provably farther than the
+// best distance found (bound > d_best), so the result is exact.
 // Returns (d << 32) | city, or ~0 if every city is visited.
 template <class Visited>
 __device__ uint64_t wave_nearest_unvisited(const GridView &g, int32_t cx, int32_t cy,
@@ -230,25 +314,29 @@ __device__ uint64_t wave_nearest_unvisited(const GridView &g, int32_t cx, int32_
     const int lane = lane_id();
     const int gx = cell_x(h, cx), gy = cell_y(h, cy);
     uint64_t best = ~0ull;
-    for (int r = 0;; ++r) {
-        const int nseg = ring_segments(r);
-        for (int sb = 0; sb < nseg; sb += kWave) {
+    int64_t s_cut = INT64_MAX;   // cities with s > s_cut cannot beat this lane's best
+    int rin = -1;
+    for (int r = 1;; rin = r, r = r + 1) {
+        const int nslots = 2 * (2 * r + 1);
+        for (int sb = 0; sb < nslots; sb += kWave) {
             const int s = sb + lane;
             int a = 0, b = 0, row, xa, xb;
-            if (s < nseg && ring_segment(h, gx, gy, r, s, row, xa, xb)) {
+            if (s < nslots && block_slot(h, gx, gy, rin, r, s, row, xa, xb)) {
                 a = g.cell_start[(int64_t)row * h.gw + xa];
                 b = g.cell_start[(int64_t)row * h.gw + xb + 1];
             }
             const int len = b - a;
-            const int incl = wave_incl_scan_i32(len, lane);
+            const int incl = wave_incl_scan_i32_dpp(len);
             const int excl = incl - len;
             const int total = read_lane_i32(incl, kWave - 1);
+            int span = nslots - sb < kWave ? nslots - sb : kWave;   // slots in this batch
+            int pw = 1;
+            while (pw < span) pw <<= 1;
             for (int base = 0; base < total; base += kWave) {
                 const int idx = base + lane;
-                // first lane whose inclusive end exceeds idx owns point idx
+                // first slot whose inclusive end exceeds idx owns flat index idx
                 int lo = 0;
-#pragma unroll
-                for (int step = kWave / 2; step > 0; step >>= 1) {
+                for (int step = pw >> 1; step > 0; step >>= 1) {
                     const int v = __shfl(incl, lo + step - 1);
                     if (v <= idx) lo += step;
                 }
@@ -256,21 +344,51 @@ __device__ uint64_t wave_nearest_unvisited(const GridView &g, int32_t cx, int32_
                 const int pe = __shfl(excl, lo);
                 if (idx < total) {
                     const int4 pt = g.pts[pa + (idx - pe)];
-                    if (!visited(pt.z)) {
-                        const uint64_t key =
-                            ((uint64_t)(uint32_t)nint_sqrt(sq_dist(cx, cy, pt.x, pt.y)) << 32) |
-                            (uint32_t)pt.z;
-                        best = key < best ? key : best;
+                    const int64_t s2 = sq_dist(cx, cy, pt.x, pt.y);
+                    if (s2 <= s_cut && !visited(pt.z)) {
+                        const uint32_t d = (uint32_t)nint_sqrt(s2);
+                        const uint64_t key = ((uint64_t)d << 32) | (uint32_t)pt.z;
+                        if (key < best) {
+                            best = key;
+                            s_cut = (int64_t)d * d + d;   // nint(sqrt(s)) <= d  <=>  s <= d^2 + d
+                        }
                     }
                 }
             }
         }
-        best = wave_min_u64(best);
+        best = wave_min_u64_dpp(best);
+        if (best != ~0ull) {
+            const int64_t d = (int64_t)(best >> 32);
+            s_cut = d * d + d;
+        }
         int64_t bound;
         if (!outside_bound(h, cx, cy, gx, gy, r, bound)) break;
         if (best != ~0ull && bound > (int64_t)(best >> 32)) break;
     }
     return best;
+}
+
+// The fallback of a step at city c when no unvisited candidate has positive
+// weight: the first unvisited city of c's extended neighbour table is the
+// nearest unvisited city (the table is in (d, index) order and holds every
+// city closer than its last entry); only when all of them are visited is the
+// grid searched.
+template <class Visited>
+__device__ int32_t fallback_city(const GridView &g, const int32_t *xy, int32_t c,
+                                 const Visited &visited)
+{
+    const int lane = lane_id();
+    const int kx = g.h.kx;
+    bool unv = false;
+    int32_t j = 0;
+    if (lane < kx) {
+        j = g.ext[(int64_t)c * kx + lane];
+        unv = !visited(j);
+    }
+    const uint64_t bal = __ballot(unv);
+    if (bal) return read_lane_i32(j, __ffsll((unsigned long long)bal) - 1);
+    const int32_t cx = xy[2 * (int64_t)c], cy = xy[2 * (int64_t)c + 1];
+    return (int32_t)(uint32_t)wave_nearest_unvisited(g, cx, cy, visited);
 }
 
 }  // namespace aco

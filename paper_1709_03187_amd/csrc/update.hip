@@ -60,28 +60,34 @@ __global__ void k_deposit(const int32_t *__restrict__ nn, const int8_t *__restri
     int r = -1;
     if (slots && t + 1 < n) {
         const uint32_t s = slots[base + t + 1];
-        if (s < (uint32_t)k && nn[ri + s] == j) r = (int)s;
+        if (s < (uint32_t)k) r = (int)s;
     }
     if (r < 0) r = find_slot(nn, ri, k, j);
-    int r2;
-    if (r >= 0) {
+    const int r2 = (r >= 0) ? (int)rev[ri + r] : find_slot(nn, rj, k, i);
+    // one atomic per undirected edge, into its canonical slot: the slot in the
+    // row of the smaller city when both directions are stored
+    if (r >= 0 && (r2 < 0 || i < j))
         atomicAdd(&acc[ri + r], qa);
-        r2 = rev[ri + r];
-    } else {
-        r2 = find_slot(nn, rj, k, i);
-    }
-    if (r2 >= 0 && r2 < k) atomicAdd(&acc[rj + r2], qa);
+    else if (r2 >= 0 && r2 < k)
+        atomicAdd(&acc[rj + r2], qa);
 }
 
 // tau = fl32(fl32(tau * f) + fl32(fl32(acc) * 2^-shift)); both products are
-// exact or singly rounded, no fused multiply-add.
-__global__ void k_merge(float *__restrict__ tau, const int64_t *__restrict__ acc, int64_t count,
-                        float f, float scale)
+// exact or singly rounded, no fused multiply-add.  The deposit of slot (i, r)
+// sits in the canonical slot of its edge: its own, or the partner slot
+// (nn[i][r], rev[i][r]) when that one lies in the row of the smaller city.
+__global__ void k_merge(float *__restrict__ tau, const int64_t *__restrict__ acc,
+                        const int32_t *__restrict__ nn, const int8_t *__restrict__ rev,
+                        int32_t k, int64_t count, float f, float scale)
 {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count;
          e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = (count <= INT32_MAX) ? (int64_t)((uint32_t)e / (uint32_t)k) : e / k;
+        const int32_t j = nn[e];
+        const int r2 = rev[e];
+        const int64_t src = (r2 >= 0 && j < i) ? (int64_t)j * k + r2 : e;
         const float evap = __fmul_rn(tau[e], f);
-        const float dep = __fmul_rn((float)acc[e], scale);
+        const float dep = __fmul_rn((float)acc[src], scale);
         tau[e] = __fadd_rn(evap, dep);
     }
 }
@@ -184,7 +190,8 @@ extern "C" int aco_update_pheromone(int32_t n, int32_t k, const int32_t *nn, con
         nn, rev, n, k, m, tours, slots, q, (unsigned long long *)acc);
     const float f = (float)(1.0 - rho);
     const float scale = std::ldexp(1.0f, -deposit_shift);
-    k_merge<<<std::min(8192u, blocks_for(nk, 256)), 256, 0, st>>>(tau, acc, nk, f, scale);
+    k_merge<<<std::min(8192u, blocks_for(nk, 256)), 256, 0, st>>>(tau, acc, nn, rev, k, nk, f,
+                                                                  scale);
     ACO_LAUNCH_CHECK("update kernels");
     return ACO_OK;
 }
