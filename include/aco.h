@@ -191,6 +191,58 @@ int aco_run(const int32_t *xy, int32_t n, const aco_params_t *p, int32_t *best_t
             int64_t *best_len, int64_t *iter_best, float *tau_out, void *ws, size_t ws_bytes,
             void *stream);
 
+/* ------------------------------------------------------------------------
+ * Batched colonies: B independent instances of uneven size, each running the
+ * loop of aco_run (same rules, same Philox keying with the ant index local to
+ * its instance), concatenated in CSR form.
+ *
+ *   xy        int32 [N][2], N = offsets[B]; instance b owns rows
+ *             offsets[b] .. offsets[b+1]-1 and numbers its cities from 0
+ *   offsets   HOST int64 [B+1], offsets[0] = 0; every n_b >= 3, n_b <= 65536,
+ *             k <= min over b of n_b - 1; 1 <= m <= 1024
+ *   best_tours int32 [N]  (output) best tour of each instance, local indices
+ *   best_lens  int64 [B]  (output)
+ *   iter_best  int64 [B][iterations] (output, may be NULL)
+ *   ws         device workspace of aco_batch_workspace_bytes(offsets, B, p)
+ *
+ * aco_batch_setup builds every instance's grid, candidate lists and
+ * nearest-neighbour tour (the best so far starts as that tour) and
+ * synchronises to report INVALID_ARG / DEGENERATE.  aco_batch_iterate then
+ * runs iterations first .. first+count-1 of every instance in ONE persistent
+ * kernel launch (no allocation, no host synchronisation: it can be captured in
+ * a HIP graph); its iter_best is [B][count].  `waves` = waves per instance
+ * workgroup (1, 2, 4, 8, 16, or 0 for the tuned value) and `vis_layout` =
+ * ACO_VIS_BITS / ACO_VIS_BYTES (0 for the tuned value) change the speed, never
+ * the results.  aco_run_batched = set-up + all iterations; with autotune != 0
+ * its first iterations each run a different configuration, timed, and the
+ * fastest (cached per device and shape) runs the rest; tuned_out (host int32
+ * [2], may be NULL) receives {waves, layout}.
+ * aco_batch_layout gives the byte offsets of the state arrays inside ws
+ * (for inspection: nn/nnd/rev/eta_b/tau are [N][k], tours/slots are instance
+ * b at m*offsets[b] as [m][n_b], lengths [B][m]).
+ * ------------------------------------------------------------------------ */
+#define ACO_VIS_BITS 1
+#define ACO_VIS_BYTES 2
+
+typedef struct aco_batch_layout {
+    size_t nn, nnd, rev, eta_b, tau, tours, slots, lengths, total;
+} aco_batch_layout_t;
+
+size_t aco_batch_workspace_bytes(const int64_t *offsets, int32_t B, const aco_params_t *p);
+int aco_batch_layout(const int64_t *offsets, int32_t B, const aco_params_t *p,
+                     aco_batch_layout_t *out);
+int aco_batch_setup(const int32_t *xy, const int64_t *offsets, int32_t B, const aco_params_t *p,
+                    int32_t *best_tours, int64_t *best_lens, void *ws, size_t ws_bytes,
+                    void *stream);
+int aco_batch_iterate(const int64_t *offsets, int32_t B, const aco_params_t *p,
+                      int32_t first_iteration, int32_t count, int32_t waves, int32_t vis_layout,
+                      int32_t *best_tours, int64_t *best_lens, int64_t *iter_best, void *ws,
+                      size_t ws_bytes, void *stream);
+int aco_run_batched(const int32_t *xy, const int64_t *offsets, int32_t B, const aco_params_t *p,
+                    int32_t autotune, int32_t *best_tours, int64_t *best_lens,
+                    int64_t *iter_best, void *ws, size_t ws_bytes, void *stream,
+                    int32_t *tuned_out);
+
 #ifdef __cplusplus
 }
 #endif

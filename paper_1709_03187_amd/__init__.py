@@ -34,8 +34,11 @@ EXPORTS = (
     "aco_strerror", "aco_last_error", "aco_version", "aco_grid_bytes", "aco_build_candidates",
     "aco_init_pheromone", "aco_construct_workspace_bytes", "aco_construct_tours",
     "aco_update_workspace_bytes", "aco_update_pheromone", "aco_track_best",
-    "aco_run_workspace_bytes", "aco_run",
+    "aco_run_workspace_bytes", "aco_run", "aco_batch_workspace_bytes", "aco_batch_layout",
+    "aco_batch_setup", "aco_batch_iterate", "aco_run_batched",
 )
+ACO_VIS_BITS = 1
+ACO_VIS_BYTES = 2
 
 
 class AcoError(RuntimeError):
@@ -48,6 +51,11 @@ class AcoParams(C.Structure):
     _fields_ = [("m", C.c_int32), ("k", C.c_int32), ("alpha", C.c_double),
                 ("beta", C.c_double), ("rho", C.c_double), ("iterations", C.c_int32),
                 ("deposit_shift", C.c_int32), ("seed", C.c_uint64)]
+
+
+class AcoBatchLayout(C.Structure):
+    _fields_ = [(f, C.c_size_t) for f in ("nn", "nnd", "rev", "eta_b", "tau", "tours", "slots",
+                                          "lengths", "total")]
 
 
 def lib():
@@ -76,6 +84,14 @@ def lib():
             "aco_track_best": (C.c_int, [i32, i32, p, p, p, p, p, p]),
             "aco_run_workspace_bytes": (sz, [i32, C.POINTER(AcoParams)]),
             "aco_run": (C.c_int, [p, i32, C.POINTER(AcoParams), p, p, p, p, p, sz, p]),
+            "aco_batch_workspace_bytes": (sz, [p, i32, C.POINTER(AcoParams)]),
+            "aco_batch_layout": (C.c_int, [p, i32, C.POINTER(AcoParams),
+                                           C.POINTER(AcoBatchLayout)]),
+            "aco_batch_setup": (C.c_int, [p, p, i32, C.POINTER(AcoParams), p, p, p, sz, p]),
+            "aco_batch_iterate": (C.c_int, [p, i32, C.POINTER(AcoParams), i32, i32, i32, i32, p,
+                                            p, p, p, sz, p]),
+            "aco_run_batched": (C.c_int, [p, p, i32, C.POINTER(AcoParams), i32, p, p, p, p, sz,
+                                          p, p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -274,3 +290,95 @@ class Colony:
         self.construct(iteration, stream)
         self.track_best(iter_best, stream)
         self.update(stream)
+
+
+# ------------------------------------------------------------ batched colonies
+def _host_i64(a):
+    import numpy as np
+    arr = np.ascontiguousarray(a, dtype=np.int64)
+    return arr, arr.ctypes.data_as(C.c_void_p)
+
+
+def aco_batch_workspace_bytes(offsets, B, params: AcoParams) -> int:
+    arr, ptr = _host_i64(offsets)
+    return int(lib().aco_batch_workspace_bytes(ptr, B, C.byref(params)))
+
+
+def aco_batch_layout(offsets, B, params: AcoParams) -> AcoBatchLayout:
+    arr, ptr = _host_i64(offsets)
+    out = AcoBatchLayout()
+    _check(lib().aco_batch_layout(ptr, B, C.byref(params), C.byref(out)))
+    return out
+
+
+def aco_batch_setup(xy, offsets, B, params, best_tours, best_lens, ws, stream=None):
+    torch = _t()
+    arr, ptr = _host_i64(offsets)
+    _check(lib().aco_batch_setup(
+        _ptr(xy, torch.int32, "xy"), ptr, B, C.byref(params),
+        _ptr(best_tours, torch.int32, "best_tours"), _ptr(best_lens, torch.int64, "best_lens"),
+        _ptr(ws, torch.uint8, "ws"), ws.numel(), _stream(stream)))
+
+
+def aco_batch_iterate(offsets, B, params, first_iteration, count, waves, vis_layout, best_tours,
+                      best_lens, iter_best, ws, stream=None):
+    torch = _t()
+    arr, ptr = _host_i64(offsets)
+    _check(lib().aco_batch_iterate(
+        ptr, B, C.byref(params), int(first_iteration), int(count), int(waves), int(vis_layout),
+        _ptr(best_tours, torch.int32, "best_tours"), _ptr(best_lens, torch.int64, "best_lens"),
+        _ptr(iter_best, torch.int64, "iter_best"), _ptr(ws, torch.uint8, "ws"), ws.numel(),
+        _stream(stream)))
+
+
+def aco_run_batched(xy, offsets, B, params, autotune, best_tours, best_lens, iter_best, ws,
+                    stream=None):
+    """Returns the (waves, layout) configuration used."""
+    torch = _t()
+    arr, ptr = _host_i64(offsets)
+    tuned = (C.c_int32 * 2)()
+    _check(lib().aco_run_batched(
+        _ptr(xy, torch.int32, "xy"), ptr, B, C.byref(params), int(autotune),
+        _ptr(best_tours, torch.int32, "best_tours"), _ptr(best_lens, torch.int64, "best_lens"),
+        _ptr(iter_best, torch.int64, "iter_best"), _ptr(ws, torch.uint8, "ws"), ws.numel(),
+        _stream(stream), tuned))
+    return int(tuned[0]), int(tuned[1])
+
+
+class Batch:
+    """Device buffers of a batch of instances (xy int32 [N, 2], offsets int64 [B+1])."""
+
+    def __init__(self, xy, offsets, k, m, alpha=1.0, beta=2.0, rho=0.1, seed=4, iterations=30,
+                 deposit_shift=32, device="cuda"):
+        torch = _t()
+        import numpy as np
+        self.offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        self.B = len(self.offsets) - 1
+        self.N = int(self.offsets[-1])
+        self.params = AcoParams(m=m, k=k, alpha=alpha, beta=beta, rho=rho, iterations=iterations,
+                                deposit_shift=deposit_shift, seed=seed)
+        self.xy = torch.as_tensor(xy, dtype=torch.int32).to(device).contiguous()
+        self.ws = torch.empty(aco_batch_workspace_bytes(self.offsets, self.B, self.params),
+                              dtype=torch.uint8, device=device)
+        self.best_tours = torch.empty(self.N, dtype=torch.int32, device=device)
+        self.best_lens = torch.empty(self.B, dtype=torch.int64, device=device)
+        self.layout = aco_batch_layout(self.offsets, self.B, self.params)
+
+    def setup(self, stream=None):
+        aco_batch_setup(self.xy, self.offsets, self.B, self.params, self.best_tours,
+                        self.best_lens, self.ws, stream)
+
+    def iterate(self, first, count, waves=0, layout=0, iter_best=None, stream=None):
+        aco_batch_iterate(self.offsets, self.B, self.params, first, count, waves, layout,
+                          self.best_tours, self.best_lens, iter_best, self.ws, stream)
+
+    def run(self, autotune=1, iter_best=None, stream=None):
+        return aco_run_batched(self.xy, self.offsets, self.B, self.params, autotune,
+                               self.best_tours, self.best_lens, iter_best, self.ws, stream)
+
+    def view(self, name, dtype, count):
+        """A tensor view of one state array inside the workspace."""
+        torch = _t()
+        off = getattr(self.layout, name)
+        size = torch.tensor([], dtype=dtype).element_size()
+        return self.ws[off:off + count * size].view(dtype)

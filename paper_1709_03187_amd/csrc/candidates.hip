@@ -8,8 +8,8 @@
 #include <cmath>
 #include <cstring>
 
+#include "colony.hpp"
 #include "common.hpp"
-#include "device.hpp"
 
 namespace aco {
 
@@ -128,42 +128,13 @@ __global__ __launch_bounds__(kKnnThreads) void k_knn(void *grid, int32_t k, int3
 {
     extern __shared__ uint64_t lists[];   // [kx][kKnnThreads]
     const GridView g = grid_view(grid);
-    const GridHdr &h = g.h;
-    const int kx = h.kx;                  // k <= kx: the candidate list is the table's prefix
+    const int kx = g.h.kx;                // k <= kx: the candidate list is the table's prefix
     int32_t *ext = (int32_t *)g.ext;
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p >= h.n) return;
+    if (p >= g.h.n) return;
     uint64_t *L = lists + threadIdx.x;
     const int4 me = g.pts[p];
-    const int gx = cell_x(h, me.x), gy = cell_y(h, me.y);
-    int cnt = 0;
-    int rin = -1;
-    for (int r = 1;; rin = r, r = 2 * r + 1) {
-        const int nslots = 2 * (2 * r + 1);
-        for (int s = 0; s < nslots; ++s) {
-            int row, xa, xb;
-            if (!block_slot(h, gx, gy, rin, r, s, row, xa, xb)) continue;
-            const int a = g.cell_start[(int64_t)row * h.gw + xa];
-            const int b = g.cell_start[(int64_t)row * h.gw + xb + 1];
-            for (int q = a; q < b; ++q) {
-                const int4 pt = g.pts[q];
-                if (pt.z == me.z) continue;
-                const uint64_t key =
-                    ((uint64_t)(uint32_t)nint_sqrt(sq_dist(me.x, me.y, pt.x, pt.y)) << 32) |
-                    (uint32_t)pt.z;
-                if (cnt == kx && key >= L[(int64_t)(kx - 1) * kKnnThreads]) continue;
-                int pos = cnt < kx ? cnt++ : kx - 1;
-                while (pos > 0 && L[(int64_t)(pos - 1) * kKnnThreads] > key) {
-                    L[(int64_t)pos * kKnnThreads] = L[(int64_t)(pos - 1) * kKnnThreads];
-                    --pos;
-                }
-                L[(int64_t)pos * kKnnThreads] = key;
-            }
-        }
-        int64_t bound;
-        if (!outside_bound(h, me.x, me.y, gx, gy, r, bound)) break;
-        if (cnt == kx && bound > (int64_t)(L[(int64_t)(kx - 1) * kKnnThreads] >> 32)) break;
-    }
+    knn_city(g, me, kx, L, kKnnThreads);
     const int64_t row = (int64_t)me.z * k, xrow = (int64_t)me.z * kx;
     for (int r = 0; r < kx; ++r) {
         const uint64_t key = L[(int64_t)r * kKnnThreads];
@@ -209,9 +180,8 @@ __global__ void k_eta(const int32_t *__restrict__ nnd, const float *__restrict__
 
 // ------------------------------------------------------------------ NN tour
 
-// The nearest-neighbour tour from city 0 by one wave: the first unvisited
-// candidate of the current city when there is one (candidate keys are smaller
-// than all others), else the exact grid search.  Visited bits live in LDS.
+// The nearest-neighbour tour from city 0 by one wave (the visited bits are the
+// workgroup's LDS).
 __global__ __launch_bounds__(kWave) void k_nn_tour(const int32_t *__restrict__ xy, int32_t n,
                                                    int32_t k, const int32_t *__restrict__ nn,
                                                    const int32_t *__restrict__ nnd,
@@ -219,51 +189,8 @@ __global__ __launch_bounds__(kWave) void k_nn_tour(const int32_t *__restrict__ x
                                                    int64_t *length)
 {
     extern __shared__ uint32_t vis[];
-    const int lane = lane_id();
-    const GridView g = grid_view(grid);
-    const int nwords = (n + 31) >> 5;
-    for (int w = lane; w < nwords; w += kWave) vis[w] = 0u;
-    __syncthreads();
-    auto visited = [&](int city) { return (vis[city >> 5] >> (city & 31)) & 1u; };
-    if (lane == 0) vis[0] = 1u;
-    int32_t c = 0;
-    int64_t L = 0;
-    int32_t stage = 0;   // lane t holds tour[base + t]
-    for (int32_t t = 1; t < n; ++t) {
-        const int64_t rb = (int64_t)c * k;
-        int32_t j = 0, d = 0;
-        bool unv = false;
-        if (lane < k) {
-            j = nn[rb + lane];
-            d = nnd[rb + lane];
-            unv = !visited(j);
-        }
-        const uint64_t bal = __ballot(unv);
-        int32_t jn, dn;
-        if (bal) {
-            const int f = __ffsll((unsigned long long)bal) - 1;
-            jn = read_lane_i32(j, f);
-            dn = read_lane_i32(d, f);
-        } else {
-            jn = fallback_city(g, xy, c, visited);
-            jn = ((uint32_t)jn < (uint32_t)n) ? jn : 0;   // range guard (see construct.hip)
-            dn = nint_sqrt(sq_dist(xy[2 * (int64_t)c], xy[2 * (int64_t)c + 1],
-                                   xy[2 * (int64_t)jn], xy[2 * (int64_t)jn + 1]));
-        }
-        jn = ((uint32_t)jn < (uint32_t)n) ? jn : 0;   // range guard (see construct.hip)
-        if (lane == 0) atomicOr(&vis[jn >> 5], 1u << (jn & 31));
-        if (lane == (t & 63)) stage = jn;
-        if ((t & 63) == 63 || t == n - 1) {
-            const int32_t base = t & ~63;
-            if (base + lane <= t) tour[base + lane] = stage;
-        }
-        L += dn;
-        c = jn;
-        __syncthreads();
-    }
-    const int64_t s = sq_dist(xy[2 * (int64_t)c], xy[2 * (int64_t)c + 1], xy[0], xy[1]);
-    L += nint_sqrt(s);
-    if (lane == 0) *length = L;
+    const int64_t L = nn_tour_wave(xy, n, k, nn, nnd, grid_view(grid), VisBits{vis}, tour);
+    if (lane_id() == 0) *length = L;
 }
 
 __global__ void k_fill_f32(float *p, int64_t count, float v)

@@ -1,0 +1,261 @@
+// Per-ant tour construction and per-row choice weights, shared by the
+// single-instance kernels and the batched persistent kernel.
+#pragma once
+
+#include "device.hpp"
+
+namespace aco {
+
+// Packed candidate row element: candidate city and its choice weight.
+struct CandW {
+    int32_t city;
+    float w;
+};
+
+// Choice weights of one row, w[r] = tau^alpha * eta_b scaled by a per-row
+// power of two (probabilities are invariant to a per-row factor).  For
+// alpha in {0, 1} the value is the exact product rounded once to FP32 (times
+// 2^E); for other alpha it is exp2(alpha log2 tau + log2 eta_b - row max).
+__device__ __forceinline__ void choice_row(const int32_t *__restrict__ nn,
+                                           const float *__restrict__ tau,
+                                           const float *__restrict__ eta_b, int k, double alpha,
+                                           CandW *__restrict__ rows)
+{
+    if (alpha == 1.0 || alpha == 0.0) {
+        double mx = 0.0;
+        for (int r = 0; r < k; ++r) {
+            const double p = (alpha == 1.0 ? (double)tau[r] : 1.0) * (double)eta_b[r];
+            mx = p > mx ? p : mx;
+        }
+        const int e = (mx > 0.0) ? -ilogb(mx) : 0;
+        for (int r = 0; r < k; ++r) {
+            const double p = (alpha == 1.0 ? (double)tau[r] : 1.0) * (double)eta_b[r];
+            rows[r] = CandW{nn[r], (float)ldexp(p, e)};
+        }
+    } else {
+        double mx = -INFINITY;
+        for (int r = 0; r < k; ++r) {
+            const double t = (double)tau[r], eb = (double)eta_b[r];
+            const double lw = (t > 0.0 && eb > 0.0) ? alpha * log2(t) + log2(eb) : -INFINITY;
+            mx = lw > mx ? lw : mx;
+        }
+        for (int r = 0; r < k; ++r) {
+            const double t = (double)tau[r], eb = (double)eta_b[r];
+            const double lw = (t > 0.0 && eb > 0.0) ? alpha * log2(t) + log2(eb) : -INFINITY;
+            rows[r] = CandW{nn[r], (float)((mx > -INFINITY) ? exp2(lw - mx) : 0.0)};
+        }
+    }
+}
+
+// Visited sets of one ant in LDS: one bit per city, or one byte per city
+// (no read-modify-write; 8x the space).  Both are private to one wave, whose
+// LDS operations complete in issue order.
+struct VisBits {
+    uint32_t *w;
+    __device__ __forceinline__ static VisBits at(void *p) { return VisBits{(uint32_t *)p}; }
+    __device__ __forceinline__ static size_t bytes(int64_t n) { return (size_t)((n + 31) / 32) * 4; }
+    __device__ __forceinline__ uint32_t test(int c) const { return (w[c >> 5] >> (c & 31)) & 1u; }
+    __device__ __forceinline__ void set(int c) const { atomicOr(&w[c >> 5], 1u << (c & 31)); }
+    __device__ __forceinline__ void clear(int n, int lane) const
+    {
+        for (int i = lane; i < ((n + 31) >> 5); i += kWave) w[i] = 0u;
+    }
+};
+
+struct VisBytes {
+    uint8_t *b;
+    __device__ __forceinline__ static VisBytes at(void *p) { return VisBytes{(uint8_t *)p}; }
+    __device__ __forceinline__ static size_t bytes(int64_t n) { return (size_t)((n + 3) & ~3); }
+    __device__ __forceinline__ uint32_t test(int c) const { return b[c]; }
+    __device__ __forceinline__ void set(int c) const { b[c] = 1; }
+    __device__ __forceinline__ void clear(int n, int lane) const
+    {
+        uint32_t *w = (uint32_t *)b;
+        for (int i = lane; i < ((n + 3) >> 2); i += kWave) w[i] = 0u;
+    }
+};
+
+struct AntTask {
+    const int32_t *xy;     // [n][2]
+    const CandW *rows;     // [n][k]
+    int32_t n, k;
+    uint32_t ant;          // absolute ant index (Philox counter word 1)
+    uint32_t iteration;    // Philox counter word 2
+    uint64_t seed;         // Philox key
+    int32_t *tour;         // [n] output
+    uint8_t *slots;        // [n] output
+    float *prob;           // [n] output or nullptr
+};
+
+// Builds one ant's tour with the whole wave (Section 2, Eq. 1).  Lane r < k
+// holds candidate r of the current city.  The critical path of a step is:
+// row load -> visited test (LDS) -> DPP scan -> ballot -> next row address.
+// (Touching the candidates' rows ahead of time does not help: vector loads
+// complete in order, so the next row load would wait for the slowest touch.)
+// KP is the scan width, the smallest power of two >= k.  `grid()` returns the
+// instance's GridView (only needed on a fallback step).
+template <int KP, class Vis, class GridFn>
+__device__ void build_ant(const AntTask &T, const Vis &vis, const GridFn &grid)
+{
+    const int lane = lane_id();
+    const int32_t n = T.n, k = T.k;
+    vis.clear(n, lane);
+    auto visited = [&](int city) { return vis.test(city); };
+    const bool want_prob = T.prob != nullptr;
+
+    // lane l holds the Philox word of step (base + l)
+    uint32_t rnd = colony_draw(T.seed, T.iteration, T.ant, (uint32_t)lane);
+    const uint32_t x0 = (uint32_t)read_lane_i32((int32_t)rnd, 0);
+    const int32_t start = (int32_t)(((uint64_t)x0 * (uint64_t)n) >> 32);
+    if (lane == 0) vis.set(start);
+
+    int32_t st_city = start;      // staged outputs: lane l holds step (base + l)
+    uint32_t st_slot = kNoSlot;
+    float st_prob = 1.0f;
+    int32_t c = start;
+    const bool active = lane < k;
+    const int lr = active ? lane : k - 1;   // idle lanes re-read a valid element
+    GridView g;
+    bool have_grid = false;
+
+    for (int32_t step = 1; step < n; ++step) {
+        if ((step & 63) == 0)
+            rnd = colony_draw(T.seed, T.iteration, T.ant, (uint32_t)(step + lane));
+        const CandW e = T.rows[(int64_t)c * k + lr];
+        const int32_t j = e.city;
+        const uint32_t seen = visited(j);          // every lane reads a valid word
+        const bool unv = active && seen == 0u;
+        const double wv = (unv && e.w > 0.0f) ? (double)e.w : 0.0;
+        const double cum = wave_incl_scan_f64(wv, KP);
+        const double S = read_lane_f64(cum, k - 1);
+        int32_t jn;
+        uint32_t slot;
+        float prob = -1.0f;
+        if (S > 0.0) {
+            const uint32_t x = (uint32_t)read_lane_i32((int32_t)rnd, step & 63);
+            const double target = (double)x * 0x1p-32 * S;
+            const uint64_t hit = __ballot(wv > 0.0 && target < cum);
+            const int f = hit ? __ffsll((unsigned long long)hit) - 1
+                              : 63 - __clzll((long long)__ballot(wv > 0.0));
+            jn = read_lane_i32(j, f);
+            slot = (uint32_t)f;
+            if (want_prob) prob = (float)(read_lane_f64(wv, f) / S);
+        } else {
+            if (!have_grid) {
+                g = grid();
+                have_grid = true;
+            }
+            jn = fallback_city(g, T.xy, c, visited);
+            slot = kNoSlot;
+        }
+        // a city index is always in range here; the clamp only keeps a logic
+        // error from turning into an out-of-bounds access (tests see the tour)
+        jn = ((uint32_t)jn < (uint32_t)n) ? jn : start;
+        if (lane == 0) vis.set(jn);
+        if (lane == (step & 63)) {
+            st_city = jn;
+            st_slot = slot;
+            st_prob = prob;
+        }
+        if ((step & 63) == 63 || step == n - 1) {
+            const int32_t base = step & ~63;
+            if (base + lane <= step) {
+                T.tour[base + lane] = st_city;
+                T.slots[base + lane] = (uint8_t)st_slot;
+                if (want_prob) T.prob[base + lane] = st_prob;
+            }
+        }
+        c = jn;
+    }
+}
+
+// The kx nearest cities of city `me` in (d, index) order, by one thread:
+// square blocks of cells of growing radius (1, 3, 7, ...), a sorted list of
+// keys (d << 32 | city) in LDS at L[0], L[ls], L[2 ls], ...; the search stops
+// once every point outside the searched block is farther than the kx-th
+// distance.  Requires kx <= (number of other cities).
+__device__ inline void knn_city(const GridView &g, const int4 me, int kx, uint64_t *L, int ls)
+{
+    const GridHdr &h = g.h;
+    const int gx = cell_x(h, me.x), gy = cell_y(h, me.y);
+    int cnt = 0;
+    int rin = -1;
+    for (int r = 1;; rin = r, r = 2 * r + 1) {
+        const int nslots = 2 * (2 * r + 1);
+        for (int s = 0; s < nslots; ++s) {
+            int row, xa, xb;
+            if (!block_slot(h, gx, gy, rin, r, s, row, xa, xb)) continue;
+            const int a = g.cell_start[(int64_t)row * h.gw + xa];
+            const int b = g.cell_start[(int64_t)row * h.gw + xb + 1];
+            for (int q = a; q < b; ++q) {
+                const int4 pt = g.pts[q];
+                if (pt.z == me.z) continue;
+                const uint64_t key =
+                    ((uint64_t)(uint32_t)nint_sqrt(sq_dist(me.x, me.y, pt.x, pt.y)) << 32) |
+                    (uint32_t)pt.z;
+                if (cnt == kx && key >= L[(int64_t)(kx - 1) * ls]) continue;
+                int pos = cnt < kx ? cnt++ : kx - 1;
+                while (pos > 0 && L[(int64_t)(pos - 1) * ls] > key) {
+                    L[(int64_t)pos * ls] = L[(int64_t)(pos - 1) * ls];
+                    --pos;
+                }
+                L[(int64_t)pos * ls] = key;
+            }
+        }
+        int64_t bound;
+        if (!outside_bound(h, me.x, me.y, gx, gy, r, bound)) break;
+        if (cnt == kx && bound > (int64_t)(L[(int64_t)(kx - 1) * ls] >> 32)) break;
+    }
+}
+
+// The nearest-neighbour tour from city 0 by one wave: the first unvisited
+// candidate of the current city when there is one (candidate keys are smaller
+// than all others), else the nearest unvisited city (64-NN table, then grid).
+// Writes the tour and returns its closed length.
+template <class Vis>
+__device__ int64_t nn_tour_wave(const int32_t *__restrict__ xy, int32_t n, int32_t k,
+                                const int32_t *__restrict__ nn, const int32_t *__restrict__ nnd,
+                                const GridView &g, const Vis &vis, int32_t *tour)
+{
+    const int lane = lane_id();
+    vis.clear(n, lane);
+    auto visited = [&](int city) { return vis.test(city); };
+    if (lane == 0) vis.set(0);
+    int32_t c = 0;
+    int64_t L = 0;
+    int32_t stage = 0;   // lane t holds tour[base + t]
+    for (int32_t t = 1; t < n; ++t) {
+        const int64_t rb = (int64_t)c * k;
+        int32_t j = 0, d = 0;
+        bool unv = false;
+        if (lane < k) {
+            j = nn[rb + lane];
+            d = nnd[rb + lane];
+            unv = !visited(j);
+        }
+        const uint64_t bal = __ballot(unv);
+        int32_t jn, dn;
+        if (bal) {
+            const int f = __ffsll((unsigned long long)bal) - 1;
+            jn = read_lane_i32(j, f);
+            dn = read_lane_i32(d, f);
+        } else {
+            jn = fallback_city(g, xy, c, visited);
+            jn = ((uint32_t)jn < (uint32_t)n) ? jn : 0;   // range guard, as in build_ant
+            dn = nint_sqrt(sq_dist(xy[2 * (int64_t)c], xy[2 * (int64_t)c + 1],
+                                   xy[2 * (int64_t)jn], xy[2 * (int64_t)jn + 1]));
+        }
+        if (lane == 0) vis.set(jn);
+        if (lane == (t & 63)) stage = jn;
+        if ((t & 63) == 63 || t == n - 1) {
+            const int32_t base = t & ~63;
+            if (base + lane <= t) tour[base + lane] = stage;
+        }
+        L += dn;
+        c = jn;
+    }
+    L += nint_sqrt(sq_dist(xy[2 * (int64_t)c], xy[2 * (int64_t)c + 1], xy[0], xy[1]));
+    return L;
+}
+
+}  // namespace aco

@@ -155,7 +155,8 @@ struct GridView {
     GridHdr h;
     const int32_t *cell_start;   // [ncell + 1]
     const int4 *pts;             // [n] {x, y, city, 0} in cell order
-    const int32_t *ext;          // [n][kx]
+    const int32_t *ext;          // [n][ext_stride], first kx entries of a row valid
+    int32_t ext_stride;
 };
 
 // Byte layout of the grid buffer (offsets aligned to 256 bytes).
@@ -185,6 +186,7 @@ __device__ __forceinline__ GridView grid_view(const void *grid)
     g.cell_start = (const int32_t *)(b + L.cell_start);
     g.pts = (const int4 *)(b + L.pts);
     g.ext = (const int32_t *)(b + L.ext);
+    g.ext_stride = g.h.kx;
     return g;
 }
 
@@ -382,7 +384,7 @@ __device__ int32_t fallback_city(const GridView &g, const int32_t *xy, int32_t c
     bool unv = false;
     int32_t j = 0;
     if (lane < kx) {
-        j = g.ext[(int64_t)c * kx + lane];
+        j = g.ext[(int64_t)c * g.ext_stride + lane];
         unv = !visited(j);
     }
     const uint64_t bal = __ballot(unv);
