@@ -234,10 +234,10 @@ int aco_batch_layout(const int64_t *offsets, int32_t B, const aco_params_t *p,
 int aco_batch_setup(const int32_t *xy, const int64_t *offsets, int32_t B, const aco_params_t *p,
                     int32_t *best_tours, int64_t *best_lens, void *ws, size_t ws_bytes,
                     void *stream);
-int aco_batch_iterate(const int64_t *offsets, int32_t B, const aco_params_t *p,
-                      int32_t first_iteration, int32_t count, int32_t waves, int32_t vis_layout,
-                      int32_t *best_tours, int64_t *best_lens, int64_t *iter_best, void *ws,
-                      size_t ws_bytes, void *stream);
+int aco_batch_iterate(const int32_t *xy, const int64_t *offsets, int32_t B,
+                      const aco_params_t *p, int32_t first_iteration, int32_t count,
+                      int32_t waves, int32_t vis_layout, int32_t *best_tours, int64_t *best_lens,
+                      int64_t *iter_best, void *ws, size_t ws_bytes, void *stream);
 int aco_run_batched(const int32_t *xy, const int64_t *offsets, int32_t B, const aco_params_t *p,
                     int32_t autotune, int32_t *best_tours, int64_t *best_lens,
                     int64_t *iter_best, void *ws, size_t ws_bytes, void *stream,

@@ -88,8 +88,8 @@ def lib():
             "aco_batch_layout": (C.c_int, [p, i32, C.POINTER(AcoParams),
                                            C.POINTER(AcoBatchLayout)]),
             "aco_batch_setup": (C.c_int, [p, p, i32, C.POINTER(AcoParams), p, p, p, sz, p]),
-            "aco_batch_iterate": (C.c_int, [p, i32, C.POINTER(AcoParams), i32, i32, i32, i32, p,
-                                            p, p, p, sz, p]),
+            "aco_batch_iterate": (C.c_int, [p, p, i32, C.POINTER(AcoParams), i32, i32, i32, i32,
+                                            p, p, p, p, sz, p]),
             "aco_run_batched": (C.c_int, [p, p, i32, C.POINTER(AcoParams), i32, p, p, p, p, sz,
                                           p, p]),
         }
@@ -320,12 +320,13 @@ def aco_batch_setup(xy, offsets, B, params, best_tours, best_lens, ws, stream=No
         _ptr(ws, torch.uint8, "ws"), ws.numel(), _stream(stream)))
 
 
-def aco_batch_iterate(offsets, B, params, first_iteration, count, waves, vis_layout, best_tours,
-                      best_lens, iter_best, ws, stream=None):
+def aco_batch_iterate(xy, offsets, B, params, first_iteration, count, waves, vis_layout,
+                      best_tours, best_lens, iter_best, ws, stream=None):
     torch = _t()
     arr, ptr = _host_i64(offsets)
     _check(lib().aco_batch_iterate(
-        ptr, B, C.byref(params), int(first_iteration), int(count), int(waves), int(vis_layout),
+        _ptr(xy, torch.int32, "xy"), ptr, B, C.byref(params), int(first_iteration), int(count),
+        int(waves), int(vis_layout),
         _ptr(best_tours, torch.int32, "best_tours"), _ptr(best_lens, torch.int64, "best_lens"),
         _ptr(iter_best, torch.int64, "iter_best"), _ptr(ws, torch.uint8, "ws"), ws.numel(),
         _stream(stream)))
@@ -369,7 +370,7 @@ class Batch:
                         self.best_lens, self.ws, stream)
 
     def iterate(self, first, count, waves=0, layout=0, iter_best=None, stream=None):
-        aco_batch_iterate(self.offsets, self.B, self.params, first, count, waves, layout,
+        aco_batch_iterate(self.xy, self.offsets, self.B, self.params, first, count, waves, layout,
                           self.best_tours, self.best_lens, iter_best, self.ws, stream)
 
     def run(self, autotune=1, iter_best=None, stream=None):

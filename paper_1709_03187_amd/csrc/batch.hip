@@ -459,13 +459,14 @@ static bool batch_layout(const int64_t *offs, int32_t B, int32_t k, int32_t m, B
     return true;
 }
 
-static BatchState batch_state(void *ws, const BatchLayoutHost &L, int32_t B, int32_t k, int32_t m)
+static BatchState batch_state(void *ws, const BatchLayoutHost &L, const int32_t *xy, int32_t B,
+                              int32_t k, int32_t m)
 {
     char *w = (char *)ws;
     BatchState S;
     S.off = (const int64_t *)(w + L.off);
     S.order = (const int32_t *)(w + L.order);
-    S.xy = nullptr;
+    S.xy = xy;
     S.hdr = (GridHdr *)(w + L.hdr);
     S.cell_start = (int32_t *)(w + L.cell_start);
     S.cursor = (int32_t *)(w + L.cursor);
@@ -545,6 +546,8 @@ static int launch_colony(const BatchState &S0, const BatchLayoutHost &L, const a
                          int32_t first, int32_t count, int waves, int layout, int32_t *best_tours,
                          int64_t *best_lens, int64_t *iter_best, int32_t ib_stride, hipStream_t st)
 {
+    if (S0.xy == nullptr || best_tours == nullptr || best_lens == nullptr)
+        return fail(ACO_ERR_INVALID_ARG, "NULL coordinates or outputs for the colony launch");
     const size_t lds = colony_lds(waves, layout, L.nmax, p->m);
     if (lds > max_lds_per_block())
         return fail(ACO_ERR_UNSUPPORTED, "batched LDS of %zu bytes exceeds the limit", lds);
@@ -620,8 +623,7 @@ extern "C" int aco_batch_setup(const int32_t *xy, const int64_t *offsets, int32_
     if (lds_init > max_lds_per_block())
         return fail(ACO_ERR_UNSUPPORTED, "visited bitmask exceeds LDS");
     hipStream_t st = as_stream(stream);
-    BatchState S = batch_state(ws, L, B, p->k, p->m);
-    S.xy = xy;
+    BatchState S = batch_state(ws, L, xy, B, p->k, p->m);
     // offsets and the largest-first processing order
     std::vector<int32_t> order(B);
     std::iota(order.begin(), order.end(), 0);
@@ -646,15 +648,16 @@ extern "C" int aco_batch_setup(const int32_t *xy, const int64_t *offsets, int32_
     return ACO_OK;
 }
 
-extern "C" int aco_batch_iterate(const int64_t *offsets, int32_t B, const aco_params_t *p,
-                                 int32_t first_iteration, int32_t count, int32_t waves,
-                                 int32_t vis_layout, int32_t *best_tours, int64_t *best_lens,
-                                 int64_t *iter_best, void *ws, size_t ws_bytes, void *stream)
+extern "C" int aco_batch_iterate(const int32_t *xy, const int64_t *offsets, int32_t B,
+                                 const aco_params_t *p, int32_t first_iteration, int32_t count,
+                                 int32_t waves, int32_t vis_layout, int32_t *best_tours,
+                                 int64_t *best_lens, int64_t *iter_best, void *ws, size_t ws_bytes,
+                                 void *stream)
 {
     clear_error();
     int rc = validate_batch(offsets, B, p);
     if (rc != ACO_OK) return rc;
-    ACO_REQUIRE(best_tours && best_lens && ws, "NULL array argument");
+    ACO_REQUIRE(xy && best_tours && best_lens && ws, "NULL array argument");
     ACO_REQUIRE(first_iteration >= 0 && count >= 0, "bad iteration range");
     ACO_REQUIRE(waves == 0 || waves == 1 || waves == 2 || waves == 4 || waves == 8 || waves == 16,
                 "waves per instance must be 0 (tuned), 1, 2, 4, 8 or 16");
@@ -674,7 +677,7 @@ extern "C" int aco_batch_iterate(const int64_t *offsets, int32_t B, const aco_pa
         if (waves == 0) waves = cfg.first;
         if (vis_layout == 0) vis_layout = cfg.second;
     }
-    BatchState S = batch_state(ws, L, B, p->k, p->m);
+    BatchState S = batch_state(ws, L, xy, B, p->k, p->m);
     return launch_colony(S, L, p, first_iteration, count, waves, vis_layout, best_tours, best_lens,
                          iter_best, count, as_stream(stream));
 }
@@ -690,7 +693,7 @@ extern "C" int aco_run_batched(const int32_t *xy, const int64_t *offsets, int32_
     BatchLayoutHost L;
     batch_layout(offsets, B, p->k, p->m, L);
     hipStream_t st = as_stream(stream);
-    BatchState S = batch_state(ws, L, B, p->k, p->m);
+    BatchState S = batch_state(ws, L, xy, B, p->k, p->m);
     int dev = 0;
     (void)hipGetDevice(&dev);
     const auto key = std::make_tuple(dev, p->k, p->m, L.nmax, B);
