@@ -96,6 +96,50 @@ def cpu_baseline(xy, cfg, tau0_gpu, threads, ants_per_thread=4):
                 fallback_share=float(res["fallbacks"].sum() / (count * (n - 1))))
 
 
+def batched_block():
+    """The batched workload: 4,096 instances, n log-uniform in [100, 5,000],
+    m = 64, k = 12, 30 iterations, one persistent launch per run.  The first
+    run tunes waves-per-instance and the visited layout; the timed run
+    repeats the 30 iterations from a fresh set-up with the tuned values."""
+    import torch
+
+    import paper_1709_03187_amd as aco
+    from paper_1709_03187_amd import instances
+
+    cfg = instances.CONFIGS["c4"]
+    xy, off, sizes = instances.make_batched("c4")
+    iters = cfg["iterations"]
+    bt = aco.Batch(xy, off, k=cfg["k"], m=cfg["m"], alpha=cfg["alpha"], beta=cfg["beta"],
+                   rho=cfg["rho"], seed=cfg["seed"], iterations=iters)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    tuned = bt.run(autotune=1)
+    torch.cuda.synchronize()
+    t_tuned_run = time.time() - t0
+    t0 = time.time()
+    bt.setup()
+    torch.cuda.synchronize()
+    t_setup = time.time() - t0
+    ib = torch.empty((bt.B, iters), dtype=torch.int64, device="cuda")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    bt.iterate(0, iters, waves=tuned[0], layout=tuned[1], iter_best=ib, occupancy=tuned[2])
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    steps = int(cfg["m"] * (sizes - 1).sum()) * iters
+    L0 = bt.best_lens.cpu().numpy()
+    return {"workload": f"{bt.B} instances, n log-uniform in [100, 5000] (sum {bt.N}), m=64, "
+                        f"k=12, 30 iterations, one persistent launch",
+            "ant_steps_per_s": steps / (ms * 1e-3), "launch_ms": ms,
+            "ms_per_iteration": ms / iters, "setup_ms": t_setup * 1e3,
+            "first_run_with_tuning_s": t_tuned_run,
+            "tuned": {"waves_per_instance": tuned[0],
+                      "visited_layout": "bits" if tuned[1] == 1 else "bytes",
+                      "waves_per_simd": tuned[2]},
+            "mean_best_len": float(L0.mean())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +147,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -220,10 +265,16 @@ def main():
         "iter_best": [int(v) for v in ib],
         "best_len": best_len,
     }
+    tau0_gpu = col.tau0
+    if not args.no_batched:
+        log("[bench] batched workload")
+        del col
+        torch.cuda.empty_cache()
+        out["batched"] = batched_block()
     if not args.no_cpu_baseline:
         threads = args.cpu_threads or max(1, min(16, os.cpu_count() or 1))
         log(f"[bench] cpu baseline with {threads} threads")
-        cb = cpu_baseline(xy, cfg, col.tau0, threads)
+        cb = cpu_baseline(xy, cfg, tau0_gpu, threads)
         out["cpu_baseline"] = {kk: cb[kk] for kk in ("value", "unit", "cores", "kind", "sample")}
         # equal wall time T = the GPU's whole run (set-up, warm-up and timed iterations).
         # Within T the oracle has at best its nearest-neighbour tour (one iteration of

@@ -211,12 +211,13 @@ int aco_run(const int32_t *xy, int32_t n, const aco_params_t *p, int32_t *best_t
  * runs iterations first .. first+count-1 of every instance in ONE persistent
  * kernel launch (no allocation, no host synchronisation: it can be captured in
  * a HIP graph); its iter_best is [B][count].  `waves` = waves per instance
- * workgroup (1, 2, 4, 8, 16, or 0 for the tuned value) and `vis_layout` =
- * ACO_VIS_BITS / ACO_VIS_BYTES (0 for the tuned value) change the speed, never
- * the results.  aco_run_batched = set-up + all iterations; with autotune != 0
- * its first iterations each run a different configuration, timed, and the
- * fastest (cached per device and shape) runs the rest; tuned_out (host int32
- * [2], may be NULL) receives {waves, layout}.
+ * workgroup (1, 2, 4, 8, 16), `vis_layout` = ACO_VIS_BITS / ACO_VIS_BYTES and
+ * `occupancy` = waves per SIMD the kernel's registers allow (4 or 8), each 0
+ * for the tuned value, change the speed, never the results.  aco_run_batched
+ * = set-up + all iterations; with autotune != 0 its first iterations each run
+ * a different configuration, timed, and the fastest (cached per device and
+ * shape) runs the rest; tuned_out (host int32 [3], may be NULL) receives
+ * {waves, layout, occupancy}.
  * aco_batch_layout gives the byte offsets of the state arrays inside ws
  * (for inspection: nn/nnd/rev/eta_b/tau are [N][k], tours/slots are instance
  * b at m*offsets[b] as [m][n_b], lengths [B][m]).
@@ -236,8 +237,9 @@ int aco_batch_setup(const int32_t *xy, const int64_t *offsets, int32_t B, const 
                     void *stream);
 int aco_batch_iterate(const int32_t *xy, const int64_t *offsets, int32_t B,
                       const aco_params_t *p, int32_t first_iteration, int32_t count,
-                      int32_t waves, int32_t vis_layout, int32_t *best_tours, int64_t *best_lens,
-                      int64_t *iter_best, void *ws, size_t ws_bytes, void *stream);
+                      int32_t waves, int32_t vis_layout, int32_t occupancy, int32_t *best_tours,
+                      int64_t *best_lens, int64_t *iter_best, void *ws, size_t ws_bytes,
+                      void *stream);
 int aco_run_batched(const int32_t *xy, const int64_t *offsets, int32_t B, const aco_params_t *p,
                     int32_t autotune, int32_t *best_tours, int64_t *best_lens,
                     int64_t *iter_best, void *ws, size_t ws_bytes, void *stream,

@@ -89,7 +89,7 @@ def lib():
                                            C.POINTER(AcoBatchLayout)]),
             "aco_batch_setup": (C.c_int, [p, p, i32, C.POINTER(AcoParams), p, p, p, sz, p]),
             "aco_batch_iterate": (C.c_int, [p, p, i32, C.POINTER(AcoParams), i32, i32, i32, i32,
-                                            p, p, p, p, sz, p]),
+                                            i32, p, p, p, p, sz, p]),
             "aco_run_batched": (C.c_int, [p, p, i32, C.POINTER(AcoParams), i32, p, p, p, p, sz,
                                           p, p]),
         }
@@ -321,12 +321,12 @@ def aco_batch_setup(xy, offsets, B, params, best_tours, best_lens, ws, stream=No
 
 
 def aco_batch_iterate(xy, offsets, B, params, first_iteration, count, waves, vis_layout,
-                      best_tours, best_lens, iter_best, ws, stream=None):
+                      occupancy, best_tours, best_lens, iter_best, ws, stream=None):
     torch = _t()
     arr, ptr = _host_i64(offsets)
     _check(lib().aco_batch_iterate(
         _ptr(xy, torch.int32, "xy"), ptr, B, C.byref(params), int(first_iteration), int(count),
-        int(waves), int(vis_layout),
+        int(waves), int(vis_layout), int(occupancy),
         _ptr(best_tours, torch.int32, "best_tours"), _ptr(best_lens, torch.int64, "best_lens"),
         _ptr(iter_best, torch.int64, "iter_best"), _ptr(ws, torch.uint8, "ws"), ws.numel(),
         _stream(stream)))
@@ -337,13 +337,13 @@ def aco_run_batched(xy, offsets, B, params, autotune, best_tours, best_lens, ite
     """Returns the (waves, layout) configuration used."""
     torch = _t()
     arr, ptr = _host_i64(offsets)
-    tuned = (C.c_int32 * 2)()
+    tuned = (C.c_int32 * 3)()
     _check(lib().aco_run_batched(
         _ptr(xy, torch.int32, "xy"), ptr, B, C.byref(params), int(autotune),
         _ptr(best_tours, torch.int32, "best_tours"), _ptr(best_lens, torch.int64, "best_lens"),
         _ptr(iter_best, torch.int64, "iter_best"), _ptr(ws, torch.uint8, "ws"), ws.numel(),
         _stream(stream), tuned))
-    return int(tuned[0]), int(tuned[1])
+    return int(tuned[0]), int(tuned[1]), int(tuned[2])
 
 
 class Batch:
@@ -369,8 +369,9 @@ class Batch:
         aco_batch_setup(self.xy, self.offsets, self.B, self.params, self.best_tours,
                         self.best_lens, self.ws, stream)
 
-    def iterate(self, first, count, waves=0, layout=0, iter_best=None, stream=None):
+    def iterate(self, first, count, waves=0, layout=0, iter_best=None, stream=None, occupancy=0):
         aco_batch_iterate(self.xy, self.offsets, self.B, self.params, first, count, waves, layout,
+                          occupancy,
                           self.best_tours, self.best_lens, iter_best, self.ws, stream)
 
     def run(self, autotune=1, iter_best=None, stream=None):

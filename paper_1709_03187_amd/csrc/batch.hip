@@ -290,8 +290,11 @@ __device__ __forceinline__ int64_t wave_min_i64_shfl(int64_t v)
     return v;
 }
 
-template <int KP, class Vis>
-__global__ __launch_bounds__(1024) void k_b_colony(BatchState S, ColonyParams P)
+// OCC = waves per SIMD the register allocation must allow (4: up to 128
+// VGPRs; 8: 64 VGPRs, spilling on the rare fallback path): the ants resident
+// per CU, one of the tuned knobs.
+template <int KP, class Vis, int OCC>
+__global__ __launch_bounds__(1024, OCC) void k_b_colony(BatchState S, ColonyParams P)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ int32_t win;
@@ -518,13 +521,18 @@ static int validate_batch(const int64_t *offs, int32_t B, const aco_params_t *p)
 
 using ColonyKernel = void (*)(BatchState, ColonyParams);
 
-static ColonyKernel colony_kernel(int k, int layout)
+template <class Vis, int OCC>
+static ColonyKernel colony_kernel_k(int k)
+{
+    return k <= 8 ? k_b_colony<8, Vis, OCC> : k <= 16 ? k_b_colony<16, Vis, OCC>
+           : k <= 32 ? k_b_colony<32, Vis, OCC> : k_b_colony<64, Vis, OCC>;
+}
+
+static ColonyKernel colony_kernel(int k, int layout, int occ)
 {
     if (layout == ACO_VIS_BYTES)
-        return k <= 8 ? k_b_colony<8, VisBytes> : k <= 16 ? k_b_colony<16, VisBytes>
-               : k <= 32 ? k_b_colony<32, VisBytes> : k_b_colony<64, VisBytes>;
-    return k <= 8 ? k_b_colony<8, VisBits> : k <= 16 ? k_b_colony<16, VisBits>
-           : k <= 32 ? k_b_colony<32, VisBits> : k_b_colony<64, VisBits>;
+        return occ == 8 ? colony_kernel_k<VisBytes, 8>(k) : colony_kernel_k<VisBytes, 4>(k);
+    return occ == 8 ? colony_kernel_k<VisBits, 8>(k) : colony_kernel_k<VisBits, 4>(k);
 }
 
 static size_t vis_stride(int layout, int64_t nmax)
@@ -538,20 +546,27 @@ static size_t colony_lds(int waves, int layout, int64_t nmax, int m)
     return (size_t)waves * vis_stride(layout, nmax) + (size_t)m * 8;
 }
 
+// A launch configuration: waves per instance workgroup, visited-set layout,
+// waves per SIMD the registers allow.  None of them changes the results.
+struct Tuning {
+    int waves, layout, occ;
+};
+
 // Tuned configuration per (device, k, m, largest n, batch size).
 static std::mutex g_tune_mu;
-static std::map<std::tuple<int, int, int, int64_t, int>, std::pair<int, int>> g_tuned;
+static std::map<std::tuple<int, int, int, int64_t, int>, Tuning> g_tuned;
 
 static int launch_colony(const BatchState &S0, const BatchLayoutHost &L, const aco_params_t *p,
-                         int32_t first, int32_t count, int waves, int layout, int32_t *best_tours,
+                         int32_t first, int32_t count, Tuning cfg, int32_t *best_tours,
                          int64_t *best_lens, int64_t *iter_best, int32_t ib_stride, hipStream_t st)
 {
     if (S0.xy == nullptr || best_tours == nullptr || best_lens == nullptr)
         return fail(ACO_ERR_INVALID_ARG, "NULL coordinates or outputs for the colony launch");
+    const int waves = cfg.waves, layout = cfg.layout;
     const size_t lds = colony_lds(waves, layout, L.nmax, p->m);
     if (lds > max_lds_per_block())
         return fail(ACO_ERR_UNSUPPORTED, "batched LDS of %zu bytes exceeds the limit", lds);
-    ColonyKernel kern = colony_kernel(p->k, layout);
+    ColonyKernel kern = colony_kernel(p->k, layout, cfg.occ);
     if (lds > 65536)
         ACO_HIP_CHECK(hipFuncSetAttribute((const void *)kern,
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -650,9 +665,9 @@ extern "C" int aco_batch_setup(const int32_t *xy, const int64_t *offsets, int32_
 
 extern "C" int aco_batch_iterate(const int32_t *xy, const int64_t *offsets, int32_t B,
                                  const aco_params_t *p, int32_t first_iteration, int32_t count,
-                                 int32_t waves, int32_t vis_layout, int32_t *best_tours,
-                                 int64_t *best_lens, int64_t *iter_best, void *ws, size_t ws_bytes,
-                                 void *stream)
+                                 int32_t waves, int32_t vis_layout, int32_t occupancy,
+                                 int32_t *best_tours, int64_t *best_lens, int64_t *iter_best,
+                                 void *ws, size_t ws_bytes, void *stream)
 {
     clear_error();
     int rc = validate_batch(offsets, B, p);
@@ -663,6 +678,8 @@ extern "C" int aco_batch_iterate(const int32_t *xy, const int64_t *offsets, int3
                 "waves per instance must be 0 (tuned), 1, 2, 4, 8 or 16");
     ACO_REQUIRE(vis_layout == 0 || vis_layout == ACO_VIS_BITS || vis_layout == ACO_VIS_BYTES,
                 "bad visited-set layout");
+    ACO_REQUIRE(occupancy == 0 || occupancy == 4 || occupancy == 8,
+                "occupancy must be 0 (tuned), 4 or 8 waves per SIMD");
     BatchLayoutHost L;
     batch_layout(offsets, B, p->k, p->m, L);
     if (ws_bytes < L.total)
@@ -670,16 +687,18 @@ extern "C" int aco_batch_iterate(const int32_t *xy, const int64_t *offsets, int3
     if (count == 0) return ACO_OK;
     int dev = 0;
     (void)hipGetDevice(&dev);
-    if (waves == 0 || vis_layout == 0) {
+    Tuning cfg{8, ACO_VIS_BITS, 4};
+    {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tuned.find(std::make_tuple(dev, p->k, p->m, L.nmax, B));
-        const std::pair<int, int> cfg = it != g_tuned.end() ? it->second : std::make_pair(8, (int)ACO_VIS_BITS);
-        if (waves == 0) waves = cfg.first;
-        if (vis_layout == 0) vis_layout = cfg.second;
+        if (it != g_tuned.end()) cfg = it->second;
     }
+    if (waves) cfg.waves = waves;
+    if (vis_layout) cfg.layout = vis_layout;
+    if (occupancy) cfg.occ = occupancy;
     BatchState S = batch_state(ws, L, xy, B, p->k, p->m);
-    return launch_colony(S, L, p, first_iteration, count, waves, vis_layout, best_tours, best_lens,
-                         iter_best, count, as_stream(stream));
+    return launch_colony(S, L, p, first_iteration, count, cfg, best_tours, best_lens, iter_best,
+                         count, as_stream(stream));
 }
 
 extern "C" int aco_run_batched(const int32_t *xy, const int64_t *offsets, int32_t B,
@@ -697,31 +716,33 @@ extern "C" int aco_run_batched(const int32_t *xy, const int64_t *offsets, int32_
     int dev = 0;
     (void)hipGetDevice(&dev);
     const auto key = std::make_tuple(dev, p->k, p->m, L.nmax, B);
-    int waves = 8, layout = ACO_VIS_BITS;
+    Tuning best{8, ACO_VIS_BITS, 4};
     int32_t it = 0;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto f = g_tuned.find(key);
         if (f != g_tuned.end()) {
-            waves = f->second.first;
-            layout = f->second.second;
+            best = f->second;
             autotune = 0;
         }
     }
     if (autotune) {
         // every candidate runs one real iteration (results do not depend on
         // the configuration); the fastest runs the rest
-        const int cand[][2] = {{4, ACO_VIS_BITS}, {8, ACO_VIS_BITS}, {16, ACO_VIS_BITS},
-                               {4, ACO_VIS_BYTES}, {8, ACO_VIS_BYTES}, {16, ACO_VIS_BYTES}};
+        const Tuning cand[] = {{4, ACO_VIS_BITS, 4},   {8, ACO_VIS_BITS, 4},
+                               {16, ACO_VIS_BITS, 4},  {4, ACO_VIS_BYTES, 4},
+                               {8, ACO_VIS_BYTES, 4},  {16, ACO_VIS_BYTES, 4},
+                               {4, ACO_VIS_BITS, 8},   {8, ACO_VIS_BITS, 8},
+                               {16, ACO_VIS_BITS, 8},  {8, ACO_VIS_BYTES, 8}};
         hipEvent_t e0, e1;
         ACO_HIP_CHECK(hipEventCreate(&e0));
         ACO_HIP_CHECK(hipEventCreate(&e1));
         float best_ms = 1e30f;
-        for (const auto &c : cand) {
+        for (const Tuning &c : cand) {
             if (it >= p->iterations) break;
-            if (colony_lds(c[0], c[1], L.nmax, p->m) > max_lds_per_block()) continue;
+            if (colony_lds(c.waves, c.layout, L.nmax, p->m) > max_lds_per_block()) continue;
             ACO_HIP_CHECK(hipEventRecord(e0, st));
-            rc = launch_colony(S, L, p, it, 1, c[0], c[1], best_tours, best_lens,
+            rc = launch_colony(S, L, p, it, 1, c, best_tours, best_lens,
                                iter_best ? iter_best + it : nullptr, p->iterations, st);
             if (rc != ACO_OK) return rc;
             ACO_HIP_CHECK(hipEventRecord(e1, st));
@@ -730,22 +751,22 @@ extern "C" int aco_run_batched(const int32_t *xy, const int64_t *offsets, int32_
             ACO_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
             if (ms < best_ms) {
                 best_ms = ms;
-                waves = c[0];
-                layout = c[1];
+                best = c;
             }
             ++it;
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tuned[key] = std::make_pair(waves, layout);
+        g_tuned[key] = best;
     }
     if (tuned_out) {
-        tuned_out[0] = waves;
-        tuned_out[1] = layout;
+        tuned_out[0] = best.waves;
+        tuned_out[1] = best.layout;
+        tuned_out[2] = best.occ;
     }
     if (it < p->iterations) {
-        rc = launch_colony(S, L, p, it, p->iterations - it, waves, layout, best_tours, best_lens,
+        rc = launch_colony(S, L, p, it, p->iterations - it, best, best_tours, best_lens,
                            iter_best ? iter_best + it : nullptr, p->iterations, st);
         if (rc != ACO_OK) return rc;
     }

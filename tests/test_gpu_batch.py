@@ -108,18 +108,19 @@ def test_batch_setup_and_iterations_match_oracle():
     assert near <= 1e-4 * steps
 
 
-CONFIGS = [(1, 1), (2, 1), (4, 1), (8, 1), (16, 1), (4, 2), (8, 2), (16, 2)]
+CONFIGS = [(1, 1, 4), (2, 1, 4), (4, 1, 4), (8, 1, 4), (16, 1, 4), (4, 2, 4), (8, 2, 4),
+           (16, 2, 4), (4, 1, 8), (16, 1, 8), (8, 2, 8)]
 
 
 def test_batch_invariance_across_configurations():
     import torch
     results = []
-    for waves, layout in CONFIGS:
-        say(f"[batch] config waves={waves} layout={layout}")
+    for waves, layout, occ in CONFIGS:
+        say(f"[batch] config waves={waves} layout={layout} occupancy={occ}")
         bt, xy, off, sizes = make_batch(48)
         bt.setup()
         ib = torch.empty((bt.B, 3), dtype=torch.int64, device="cuda")
-        bt.iterate(0, 3, waves=waves, layout=layout, iter_best=ib)
+        bt.iterate(0, 3, waves=waves, layout=layout, iter_best=ib, occupancy=occ)
         S = state(bt)
         results.append((S["tau"], S["best_lens"], S["best_tours"], ib.cpu().numpy()))
     for r in results[1:]:
@@ -132,7 +133,7 @@ def test_batch_autotuned_run_equals_fixed_configuration():
     bt, xy, off, sizes = make_batch(40, iterations=9)
     ib = torch.empty((bt.B, 9), dtype=torch.int64, device="cuda")
     tuned = bt.run(autotune=1, iter_best=ib)
-    assert tuned[0] in (4, 8, 16) and tuned[1] in (1, 2)
+    assert tuned[0] in (4, 8, 16) and tuned[1] in (1, 2) and tuned[2] in (4, 8)
     A = state(bt)
     bt2, *_ = make_batch(40, iterations=9)
     bt2.setup()
