@@ -1,0 +1,231 @@
+"""Pins of the learned-heuristic oracle (edge features, MLP forward/backward).
+
+Pins, none of which re-runs the oracle's own formulas:
+  * BF16 rounding equals torch's float32 -> bfloat16 conversion (ties to even);
+  * features of a hand-worked five-city instance;
+  * exact invariances of the features under integer rotation and translation;
+  * forward equals an independent torch float64 network;
+  * the FP64 gradient equals central finite differences of the loss;
+  * the quantised gradient equals torch autograd through straight-through
+    BF16 rounding points placed where the matrix cores round;
+  * labels from a tour: brute force over the tour's edges."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from oracle import mlp
+from paper_1709_03187_amd import instances
+
+torch = pytest.importorskip("torch")
+
+
+def test_bf16_rounding_matches_torch():
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.normal(0, 1, 5000), rng.normal(0, 1e-3, 1000), rng.normal(0, 1e4, 1000)])
+    x = x.astype(np.float32)
+    # exact ties: low 16 bits 0x8000 with even and odd upper parts
+    e = rng.integers(100, 150, 400, dtype=np.uint32) << np.uint32(23)
+    mant = rng.integers(0, 128, 400, dtype=np.uint32) << np.uint32(16)
+    sign = rng.integers(0, 2, 400, dtype=np.uint32) << np.uint32(31)
+    ties = (sign | e | mant | np.uint32(0x8000)).view(np.float32)
+    assert (mant & np.uint32(0x10000)).any() and not (mant & np.uint32(0x10000)).all()
+    x = np.concatenate([x, ties, np.float32([0.0, -0.0, 1.0, -1.0, 3.0e38])])
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float32).numpy()
+    np.testing.assert_array_equal(mlp.bf16(x).view(np.uint32), ref.view(np.uint32))
+
+
+def five_cities():
+    xy = np.array([[0, 0], [3, 4], [-6, -8], [20, 0], [0, 30]], np.int32)
+    nn, nnd = orc.knn_rows(xy, 3)
+    return xy, nn, nnd, orc.rev(nn)
+
+
+def test_features_hand_worked_instance():
+    """City 0 at the origin has candidates (3,4), (-6,-8), (20,0) at distances
+    5, 10, 20; the sum of the candidate offsets is c = (17, -4), |c| = sqrt(305).
+    The k-th candidate distances of the five cities are 20, 17, 27, 27, 36
+    (mean 25.4).  City 0 is rank 0 in the lists of cities 1 and 2, rank 1 in
+    that of city 3; city 4 is absent from the list of city 1."""
+    xy, nn, nnd, rev = five_cities()
+    assert nn[0].tolist() == [1, 2, 3] and nnd[0].tolist() == [5, 10, 20]
+    f = mlp.features(xy, nn, nnd, rev)
+    s = math.sqrt(305.0)
+    mean = 127.0 / 5.0
+    want = np.array([
+        [1.0, 0.25, 0.0, 0.0, 7 / s, -16 / s, 20 / mean, 17 / mean],
+        [2.0, 0.50, 0.5, 0.0, -7 / s, 16 / s, 20 / mean, 27 / mean],
+        [4.0, 1.00, 1.0, 0.5, 17 / s, -4 / s, 20 / mean, 27 / mean],
+    ], np.float64)
+    np.testing.assert_allclose(f[0], want.astype(np.float32), rtol=1.2e-7, atol=0)
+    assert nn[4, 0] == 1 and f[4, 0, 3] == 1.0          # 4 is absent from city 1's list
+    cs = f[..., 4].astype(np.float64) ** 2 + f[..., 5].astype(np.float64) ** 2
+    np.testing.assert_allclose(cs, 1.0, rtol=1e-6)
+
+
+def test_features_invariances():
+    xy = instances.uniform_coords(400, 5, hi=100000)
+    k = 10
+    nn, nnd = orc.knn_rows(xy, k)
+    f = mlp.features(xy, nn, nnd, orc.rev(nn))
+    # rotation by 90 degrees and translation: the same neighbour lists, the same bits
+    rot = np.stack([-xy[:, 1], xy[:, 0]], 1).astype(np.int32) + np.int32(12345)
+    nn2, nnd2 = orc.knn_rows(rot, k)
+    assert np.array_equal(nn, nn2) and np.array_equal(nnd, nnd2)
+    f2 = mlp.features(rot, nn2, nnd2, orc.rev(nn2))
+    np.testing.assert_array_equal(f.view(np.uint32), f2.view(np.uint32))
+    # mirror: sin changes sign, the rest is unchanged
+    mir = np.stack([-xy[:, 0], xy[:, 1]], 1).astype(np.int32)
+    nn3, nnd3 = orc.knn_rows(mir, k)
+    f3 = mlp.features(mir, nn3, nnd3, orc.rev(nn3))
+    np.testing.assert_array_equal(f3[..., 5], -f[..., 5])
+    np.testing.assert_array_equal(f3[..., [0, 1, 2, 3, 4, 6, 7]], f[..., [0, 1, 2, 3, 4, 6, 7]])
+    # ranges
+    assert (f[..., 0] >= 1).all() and (f[..., 1] <= 1).all() and (f[..., 1] > 0).all()
+    np.testing.assert_array_equal(f[:, :, 2], np.broadcast_to(np.arange(k) / (k - 1), (400, k)).astype(np.float32))
+    assert ((f[..., 3] >= 0) & (f[..., 3] <= 1)).all()
+    np.testing.assert_allclose(f[..., 6].mean(), 1.0, rtol=1e-6)
+
+
+def _torch_net(theta, X, quantize):
+    """Independent float64 torch network; BF16 rounding points as straight-
+    through functions whose backward rounds the incoming gradient where the
+    matrix cores consume it in BF16."""
+    P = mlp.unpack(theta)
+
+    def rb(t):  # round a float64 tensor to bf16 through float32
+        return t.to(torch.float32).to(torch.bfloat16).to(torch.float64)
+
+    class Act(torch.autograd.Function):     # value rounded, gradient passes
+        @staticmethod
+        def forward(ctx, t):
+            return rb(t) if quantize else t.clone()
+
+        @staticmethod
+        def backward(ctx, g):
+            return g
+
+    class Lin(torch.autograd.Function):
+        """y = x W^T + b; W's and x's gradients use BF16-rounded dy."""
+        @staticmethod
+        def forward(ctx, x, W, b):
+            ctx.save_for_backward(x, W)
+            return x @ W.t() + b
+
+        @staticmethod
+        def backward(ctx, g):
+            x, W = ctx.saved_tensors
+            gq = rb(g) if quantize else g
+            return gq @ W, gq.t() @ x, g.sum(0)
+
+    w = {key: torch.tensor(np.asarray(v, np.float64), requires_grad=True) for key, v in P.items()}
+    wq = {key: (rb(w[key].detach()) if quantize else w[key].detach()) for key in ("W1", "W2", "W3")}
+    # weights enter as BF16 values; their gradient flows straight through
+    W1 = w["W1"] + (wq["W1"] - w["W1"].detach())
+    W2 = w["W2"] + (wq["W2"] - w["W2"].detach())
+    W3 = w["W3"] + (wq["W3"] - w["W3"].detach())
+    x = Act.apply(torch.tensor(np.asarray(X, np.float64)))
+    # both hidden layers feed the gradient of their pre-activation unrounded
+    # into the bias and rounded into the weight/input products: Lin does that
+    h1 = Act.apply(torch.relu(Lin.apply(x, W1, w["b1"])))
+    h2 = Act.apply(torch.relu(Lin.apply(h1, W2, w["b2"])))
+    z = h2 @ W3 + w["b3"]
+    return z, w
+
+
+def _theta_and_data(seed, E=300):
+    rng = np.random.default_rng(seed)
+    theta = mlp.init_theta(seed)
+    theta[512:576] = rng.normal(0, 0.1, 64)
+    theta[4672:4736] = rng.normal(0, 0.1, 64)
+    theta[4800] = -1.0
+    X = rng.normal(0.5, 0.5, (E, 8)).astype(np.float32)
+    y = (rng.random(E) < 0.15).astype(np.uint8)
+    return theta, X, y
+
+
+@pytest.mark.parametrize("quantize", [False, True])
+def test_forward_matches_torch(quantize):
+    theta, X, y = _theta_and_data(1)
+    z = mlp.forward(theta, X, quantize)
+    zt, _ = _torch_net(theta, X, quantize)
+    np.testing.assert_allclose(z, zt.detach().numpy(), rtol=1e-12, atol=1e-12)
+
+
+def test_gradient_matches_finite_differences():
+    theta, X, y = _theta_and_data(2, E=64)
+    t64 = theta.astype(np.float64)
+    L, g = mlp.backward(t64, X, y, 3.0, quantize=False)
+    # FP64 parameters: evaluate the loss with a float64 parameter vector
+    rng = np.random.default_rng(3)
+    idx = np.concatenate([rng.choice(np.arange(0, 512), 20, replace=False),
+                          rng.choice(np.arange(512, 576), 8, replace=False),
+                          rng.choice(np.arange(576, 4672), 30, replace=False),
+                          rng.choice(np.arange(4672, 4736), 8, replace=False),
+                          rng.choice(np.arange(4736, 4800), 8, replace=False), [4800]])
+
+    def loss64(t):
+        P = dict(W1=t[0:512].reshape(64, 8), b1=t[512:576], W2=t[576:4672].reshape(64, 64),
+                 b2=t[4672:4736], W3=t[4736:4800], b3=t[4800])
+        x = X.astype(np.float64)
+        h1 = np.maximum(x @ P["W1"].T + P["b1"], 0)
+        h2 = np.maximum(h1 @ P["W2"].T + P["b2"], 0)
+        z = h2 @ P["W3"] + P["b3"]
+        w = np.where(y > 0, 3.0, 1.0)
+        return np.mean(w * (np.logaddexp(0, z) - y * z))
+
+    assert abs(loss64(t64) - L) < 1e-12
+    h = 1e-6
+    for i in idx:
+        tp, tm = t64.copy(), t64.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (loss64(tp) - loss64(tm)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-7 + 1e-5 * abs(g[i]), (i, fd, g[i])
+
+
+def test_quantised_gradient_matches_torch_autograd():
+    theta, X, y = _theta_and_data(4)
+    L, g = mlp.backward(theta, X, y, 5.0, quantize=True)
+    z, w = _torch_net(theta, X, True)
+    yt = torch.tensor(y, dtype=torch.float64)
+    wt = torch.where(yt > 0.5, 5.0, 1.0)
+    loss = (wt * torch.nn.functional.binary_cross_entropy_with_logits(z, yt, reduction="none")).mean()
+    loss.backward()
+    assert abs(loss.item() - L) < 1e-12
+    tg = np.concatenate([w[key].grad.numpy().ravel() for key in ("W1", "b1", "W2", "b2", "W3")]
+                        + [np.atleast_1d(w["b3"].grad.numpy())])
+    np.testing.assert_allclose(g, tg, rtol=1e-9, atol=1e-14)
+
+
+def test_first_layer_input_gradient_rounding_matters():
+    """Sanity: the quantised gradient differs from the FP64 one (the rounding
+    points are live), but only by about BF16 precision."""
+    theta, X, y = _theta_and_data(5)
+    _, gq = mlp.backward(theta, X, y, 2.0, True)
+    _, gf = mlp.backward(theta, X, y, 2.0, False)
+    assert not np.array_equal(gq, gf)
+    assert np.abs(gq - gf).max() <= 0.05 * np.abs(gf).max()
+
+
+def test_labels_from_tour_brute_force():
+    xy = instances.uniform_coords(60, 9)
+    nn, nnd = orc.knn_rows(xy, 8)
+    rng = np.random.default_rng(1)
+    tour = rng.permutation(60)
+    y = mlp.labels_from_tour(nn, tour)
+    edges = {frozenset((int(tour[t]), int(tour[(t + 1) % 60]))) for t in range(60)}
+    for i in range(60):
+        for r in range(8):
+            assert y[i, r] == (frozenset((i, int(nn[i, r]))) in edges)
+    assert (y.sum(1) <= 2).all()
+
+
+def test_sensitivity_flag_marks_values_near_bf16_midpoints():
+    mid = np.float64(1.0 + 2.0**-8)                       # halfway between 1 and next bf16
+    v = np.array([[mid, 1.0 + 2.0**-9]])
+    s = np.ones_like(v)
+    flags = mlp._near_bf16_boundary(v, s, 2.0**-20)
+    assert flags.tolist() == [[True, False]]
+    assert mlp._near_bf16_boundary(np.array([1e-9]), np.array([1.0]), 2.0**-20)[0]
