@@ -111,24 +111,22 @@ def features(xy, nn, nnd, rev) -> np.ndarray:
 
 
 # ---------------------------------------------------------------- network
-def _near_bf16_boundary(v, scale, rel):
-    """True where FP32 accumulation error (<= rel * scale) could move v across a
-    BF16 rounding midpoint (or across 0 for the ReLU)."""
+def near_bf16_step(v, delta):
+    """True where moving v by up to `delta` could change relu-then-BF16 of it:
+    a BF16 rounding midpoint or 0 lies within delta, or delta spans a BF16 step."""
     v = np.asarray(v, np.float64)
-    f = v.astype(np.float32)
-    u = f.view(np.uint32).astype(np.int64)
-    lo = (u >> 16) << 16
-    mid = (lo + 0x8000).astype(np.uint32).view(np.float32).astype(np.float64)
-    # midpoints between adjacent BF16 values around v (for negative v the bit
-    # pattern grows with magnitude, the same formula applies to |v|)
-    return (np.abs(v - np.sign(v) * np.abs(mid)) <= rel * scale) | (np.abs(v) <= rel * scale)
+    delta = np.asarray(delta, np.float64)
+    a = np.abs(v).astype(np.float32)
+    u = a.view(np.uint32).astype(np.int64)
+    lo = ((u >> 16) << 16).astype(np.uint32).view(np.float32).astype(np.float64)
+    step = (((u >> 16) + 1) << 16).astype(np.uint32).view(np.float32).astype(np.float64) - lo
+    off = np.abs(np.abs(v) - (lo + 0.5 * step))         # distance to the midpoint of v's step
+    return (off <= delta) | (step - off <= delta) | (np.abs(v) <= delta) | (delta >= 0.25 * step)
 
 
 def forward(theta, X, quantize=True, want_cache=False):
     """Logits z [E] for FP32 features X [E, 8]; FP64 arithmetic.
-    With quantize, operands are BF16 as on the matrix cores.  The cache also
-    holds `sensitive` [E]: edges where a hidden value lies within the FP32
-    accumulation error of a BF16 rounding boundary (or of 0)."""
+    With quantize, operands are BF16 as on the matrix cores."""
     P = unpack(theta)
     q = bf16 if quantize else (lambda a: np.asarray(a, np.float32))
     W1, W2, W3 = (q(P[w]).astype(np.float64) for w in ("W1", "W2", "W3"))
@@ -145,10 +143,33 @@ def forward(theta, X, quantize=True, want_cache=False):
     z = h2b @ W3 + b3
     if not want_cache:
         return z
-    sens = (_near_bf16_boundary(a1, s1, 2.0**-19).any(1) |
-            _near_bf16_boundary(a2, s2, 2.0**-16).any(1))
-    return z, dict(xb=xb, a1=a1, h1b=h1b, a2=a2, h2b=h2b, W1=W1, W2=W2, W3=W3,
-                   sensitive=sens)
+    return z, dict(xb=xb, a1=a1, s1=s1, h1b=h1b, a2=a2, s2=s2, h2b=h2b, W1=W1, W2=W2, W3=W3,
+                   b3=b3)
+
+
+# Worst-case relative error of an FP32 sum of K exact products plus a bias,
+# in any order: (K + 1) 2^-24 of the sum of magnitudes, taken with a factor 2
+# of margin (K = 8, 64, 64 for the three layers).
+GAMMA1, GAMMA2 = 2.0**-20, 2.0**-17
+
+
+def forward_bound(theta, X):
+    """(z, dz, flip) for an implementation that forms the same BF16 operands
+    but accumulates in FP32 in another order: |z_impl - z| <= dz.  A hidden
+    value whose FP32 error could cross a BF16 rounding point (or 0) may round
+    differently; `flip` marks the edges where that is possible, and dz then
+    carries the propagated change (one BF16 step, 2^-7 relative at most)."""
+    z, c = forward(theta, X, True, want_cache=True)
+    aW2, aW3 = np.abs(c["W2"]), np.abs(c["W3"])
+    d1 = GAMMA1 * c["s1"]
+    n1 = near_bf16_step(c["a1"], d1)
+    dh1 = np.where(n1, d1 + 2.0**-7 * (np.abs(c["a1"]) + d1), 0.0)
+    d2 = GAMMA2 * (c["s2"] + dh1 @ aW2.T) + dh1 @ aW2.T
+    n2 = near_bf16_step(c["a2"], d2)
+    dh2 = np.where(n2, d2 + 2.0**-7 * (np.abs(c["a2"]) + d2), 0.0)
+    Sz = np.abs(c["h2b"]) @ aW3 + abs(c["b3"])
+    dz = GAMMA2 * (Sz + dh2 @ aW3) + dh2 @ aW3
+    return z, dz, n1.any(1) | n2.any(1)
 
 
 def sigmoid(z):
@@ -194,3 +215,43 @@ def labels_from_tour(nn, tour) -> np.ndarray:
     nxt[t] = np.roll(t, -1)
     prv[t] = np.roll(t, 1)
     return ((nn == nxt[:, None]) | (nn == prv[:, None])).astype(np.uint8)
+
+
+def backward_scale(theta, X, y, pos_weight):
+    """S_p = sum over edges of |term| for every gradient entry p: the gradient
+    formulas of `backward` with every factor replaced by its absolute value.
+    Scales the error bound of an FP32-accumulated gradient."""
+    z, c = forward(theta, X, True, want_cache=True)
+    y = np.asarray(y, np.float64)
+    E = len(y)
+    w = np.where(y > 0.5, pos_weight, 1.0)
+    g = np.abs(w * (sigmoid(z) - y) / E)
+    aW2, aW3 = np.abs(c["W2"]), np.abs(c["W3"])
+    S = np.zeros(NPARAM, np.float64)
+    S[OFF["W3"]:OFF["W3"] + H] = g @ c["h2b"]
+    S[OFF["b3"]] = g.sum()
+    d2 = (g[:, None] * aW3[None, :]) * (c["a2"] > 0)
+    S[OFF["W2"]:OFF["W2"] + H * H] = (d2.T @ c["h1b"]).ravel()
+    S[OFF["b2"]:OFF["b2"] + H] = d2.sum(0)
+    d1 = (d2 @ aW2) * (c["a1"] > 0)
+    S[OFF["W1"]:OFF["W1"] + H * F] = (d1.T @ np.abs(c["xb"])).ravel()
+    S[OFF["b1"]:OFF["b1"] + H] = d1.sum(0)
+    return S
+
+
+def adam_step(theta, m, v, grad, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update (Kingma and Ba, Algorithm 1) in FP32: moments, bias
+    corrections, parameter step.  beta1 and beta2 are FP32 values, used as
+    such in the moments and (powers in FP64, rounded once) in the bias
+    corrections.  Returns new (theta, m, v)."""
+    f = np.float32
+    t, m, v, g = (np.asarray(a, f) for a in (theta, m, v, grad))
+    b1, b2 = f(beta1), f(beta2)
+    m = b1 * m + (f(1) - b1) * g
+    v = b2 * v + (f(1) - b2) * (g * g)
+    c1 = f(1.0 - float(b1) ** step)
+    c2 = f(1.0 - float(b2) ** step)
+    mh = m / c1
+    vh = v / c2
+    t = t - f(lr) * mh / (np.sqrt(vh) + f(eps))
+    return t.astype(f), m.astype(f), v.astype(f)

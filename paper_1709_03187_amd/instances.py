@@ -116,3 +116,64 @@ def make_batched(name: str = "c4", count: int | None = None):
         sizes = sizes[:count]
     xy, offsets = batched_coords(sizes, cfg["seed"])
     return xy, offsets, sizes
+
+
+def _uniform01(seed: int, tag: int, count: int) -> np.ndarray:
+    """`count` FP64 uniforms in [0, 1) with 53 random bits each."""
+    return (_raw(seed, tag, count) >> np.uint64(11)).astype(np.float64) * 2.0**-53
+
+
+# Block (offset, size, half-width) of the edge-scoring network's parameters,
+# in the order W1 [64][8], b1, W2 [64][64], b2, W3 [64], b3; the half-widths
+# are the uniform He/Glorot ranges sqrt(6 / fan_in), sqrt(3 / fan_in).
+MLP_BLOCKS = ((0, 512, math.sqrt(6 / 8)), (512, 64, 0.1), (576, 4096, math.sqrt(6 / 64)),
+              (4672, 64, 0.1), (4736, 64, math.sqrt(3 / 64)), (4800, 1, 0.1))
+MLP_PARAMS = 4801
+
+
+def mlp_parameters(seed: int, tag: int = 50) -> np.ndarray:
+    """Initial FP32 parameters of the edge-scoring network, uniform per block."""
+    u = _uniform01(seed, tag, MLP_PARAMS)
+    theta = np.empty(MLP_PARAMS, np.float64)
+    for off, size, half in MLP_BLOCKS:
+        theta[off:off + size] = (2.0 * u[off:off + size] - 1.0) * half
+    return theta.astype(np.float32)
+
+
+def mlp_edge_batch(E: int, seed: int, positive: float = 0.15, tag: int = 60):
+    """Synthetic network inputs: FP32 features [E, 8] in the ranges the edge
+    features take (ratios >= 1 and <= 1, ranks and rev in [0, 1], a unit
+    direction, local radii around 1) and uint8 labels with P(1) = positive."""
+    u = _uniform01(seed, tag, 9 * E).reshape(E, 9)
+    X = np.empty((E, 8), np.float64)
+    X[:, 0] = 1.0 + 7.0 * u[:, 0]
+    X[:, 1] = u[:, 1]
+    X[:, 2] = np.floor(16.0 * u[:, 2]) / 15.0
+    X[:, 3] = np.where(u[:, 3] < 0.3, 1.0, u[:, 3])
+    ang = 2.0 * math.pi * u[:, 4]
+    X[:, 4] = np.cos(ang)
+    X[:, 5] = np.sin(ang)
+    X[:, 6] = 0.3 + 2.7 * u[:, 5]
+    X[:, 7] = 0.3 + 2.7 * u[:, 6]
+    y = (u[:, 8] < positive).astype(np.uint8)
+    return X.astype(np.float32), y
+
+
+def mlp_dyadic_batch(E: int, seed: int, positive: float = 0.15, tag: int = 70):
+    """Parameters, features and labels on coarse dyadic grids: features
+    j/8 in [0, 2), W1 j/16 and b1 j/128 in [-1/2, 1/2], W2, W3 j/8 in
+    [-1/2, 1/2], b2 j/1024, b3 j/8192 in [-1/2, 1/2].  Products and partial
+    sums of the network then need few enough bits that FP32 holds them
+    exactly for the magnitudes these draws produce."""
+    u = _uniform01(seed, tag, MLP_PARAMS + 9 * E)
+    def grid(v, denom, half):
+        return np.floor(v * (2 * half * denom + 1)) / denom - half
+    t = np.empty(MLP_PARAMS, np.float64)
+    blocks = ((0, 512, 16), (512, 64, 128), (576, 4096, 8), (4672, 64, 1024), (4736, 64, 8),
+              (4800, 1, 8192))
+    for off, size, denom in blocks:
+        t[off:off + size] = grid(u[off:off + size], denom, 0.5)
+    w = u[MLP_PARAMS:].reshape(E, 9)
+    X = np.floor(w[:, :8] * 16) / 8
+    y = (w[:, 8] < positive).astype(np.uint8)
+    return t.astype(np.float32), X.astype(np.float32), y

@@ -222,10 +222,77 @@ def test_labels_from_tour_brute_force():
     assert (y.sum(1) <= 2).all()
 
 
-def test_sensitivity_flag_marks_values_near_bf16_midpoints():
-    mid = np.float64(1.0 + 2.0**-8)                       # halfway between 1 and next bf16
-    v = np.array([[mid, 1.0 + 2.0**-9]])
-    s = np.ones_like(v)
-    flags = mlp._near_bf16_boundary(v, s, 2.0**-20)
-    assert flags.tolist() == [[True, False]]
-    assert mlp._near_bf16_boundary(np.array([1e-9]), np.array([1.0]), 2.0**-20)[0]
+def test_near_bf16_step_flags_midpoints_and_zero():
+    mid = 1.0 + 2.0**-8                                   # halfway between 1 and the next bf16
+    v = np.array([mid, 1.0 + 2.0**-9, -mid, 1e-9, 3.0])
+    d = np.full(5, 2.0**-20)
+    assert mlp.near_bf16_step(v, d).tolist() == [True, False, True, True, False]
+    assert mlp.near_bf16_step(np.array([3.0]), np.array([0.01]))[0]   # window spans a step
+
+
+def _fp32_forward(theta, X, reverse):
+    """The network with BF16 operands and sequential FP32 accumulation
+    (bias first), in forward or reverse term order: an implementation that
+    differs from the oracle only in rounding order."""
+    P = mlp.unpack(theta)
+    f = np.float32
+    W1, W2, W3 = (mlp.bf16(P[w]) for w in ("W1", "W2", "W3"))
+    x = mlp.bf16(X)
+
+    def layer(inp, W, b):
+        acc = np.broadcast_to(np.asarray(b, f), (inp.shape[0], W.shape[0])).copy()
+        ks = range(W.shape[1])
+        for kk in (reversed(ks) if reverse else ks):
+            acc = (acc + (inp[:, kk:kk + 1] * W[None, :, kk]).astype(f)).astype(f)
+        return acc
+
+    h1 = mlp.bf16(np.maximum(layer(x, W1, P["b1"]), 0))
+    h2 = mlp.bf16(np.maximum(layer(h1, W2, P["b2"]), 0))
+    return layer(h2, W3[None, :], np.float32(P["b3"]))[:, 0]
+
+
+@pytest.mark.parametrize("reverse", [False, True])
+def test_forward_bound_covers_fp32_accumulation(reverse):
+    theta = instances.mlp_parameters(31)
+    X, _ = instances.mlp_edge_batch(3000, 32)
+    z, dz, flip = mlp.forward_bound(theta, X)
+    z32 = _fp32_forward(theta, X, reverse).astype(np.float64)
+    assert (np.abs(z32 - z) <= dz).all(), np.max(np.abs(z32 - z) / dz)
+    # the bound is tight where no rounding can flip
+    assert np.median(dz[~flip] / (np.abs(z[~flip]) + 1)) < 1e-4
+
+
+def test_dyadic_inputs_are_exact():
+    """On the dyadic parameter set every sum is exact in FP32, so any
+    accumulation order gives the oracle's logits bit for bit."""
+    theta, X, y = instances.mlp_dyadic_batch(2000, 3)
+    z = mlp.forward(theta, X, True)
+    for rev in (False, True):
+        np.testing.assert_array_equal(_fp32_forward(theta, X, rev).astype(np.float64), z)
+
+
+def test_adam_matches_torch_optimizer():
+    rng = np.random.default_rng(7)
+    theta = rng.normal(0, 1, mlp.NPARAM).astype(np.float32)
+    p = torch.nn.Parameter(torch.tensor(theta))
+    # eps comparable to sqrt(v) so that its placement matters; distinct betas
+    opt = torch.optim.Adam([p], lr=1e-3, betas=(0.8, 0.99), eps=1e-3)
+    t, m, v = theta.copy(), np.zeros_like(theta), np.zeros_like(theta)
+    for step in range(1, 6):
+        g = rng.normal(0, 1e-2, mlp.NPARAM).astype(np.float32)
+        p.grad = torch.tensor(g)
+        opt.step()
+        t, m, v = mlp.adam_step(t, m, v, g, step, 1e-3, 0.8, 0.99, 1e-3)
+        # torch forms 1 - beta^step in FP32 (relative error up to 2^-24 / (1 - beta2)),
+        # which moves its step by up to ~1e-5 of lr
+        np.testing.assert_allclose(t, p.detach().numpy(), rtol=1e-6, atol=2e-8)
+
+
+def test_backward_scale_bounds_the_gradient():
+    theta, X, y = _theta_and_data(6)
+    _, g = mlp.backward(theta, X, y, 4.0, True)
+    S = mlp.backward_scale(theta, X, y, 4.0)
+    # the gradient uses BF16-rounded d2 and d1 (each within 2^-9 relative of the
+    # unrounded values the scale uses)
+    assert (np.abs(g) <= S * (1 + 2.0**-6) + 1e-300).all()
+    assert (S > 0).mean() > 0.5
