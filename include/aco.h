@@ -245,6 +245,87 @@ int aco_run_batched(const int32_t *xy, const int64_t *offsets, int32_t B, const 
                     int64_t *iter_best, void *ws, size_t ws_bytes, void *stream,
                     int32_t *tuned_out);
 
+/* ------------------------------------------------------------------------
+ * Learned heuristic.  A small network scores every candidate edge from its
+ * local geometry, and sigmoid(score) replaces eta = 1/d in the weights
+ * tau^alpha * eta^beta of Eq. 1 (Section 2); the colony itself is unchanged.
+ *
+ * Features: FP32 [n][k][8] for candidate r of city i (j = nn[i][r], d_ir =
+ * nnd[i][r], K = k - 1, or 1 when k = 1):
+ *   0  d_ir / max(d_i0, 1)        1  d_ir / max(d_iK, 1)
+ *   2  r / K                      3  rev[i][r] / K, or 1 if i is not in j's list
+ *   4  cos, 5 sin of the angle from the edge i->j to c = sum over i's
+ *      candidates s of (p_s - p_i) (cos 1, sin 0 when either vector is zero)
+ *   6  d_iK / mean_c d_cK         7  d_jK / mean_c d_cK (both 1 if the mean is 0)
+ * Each is an exactly rounded FP64 expression of integers, rounded once to FP32.
+ *
+ * Network (ACO_MLP_PARAMS FP32 parameters theta, row-major blocks at the
+ * offsets below): W1 [64][8], b1 [64], W2 [64][64], b2 [64], W3 [64], b3.
+ * Weights W1, W2, W3 are rounded to BF16 (nearest-even) where they are used;
+ * biases and accumulation are FP32; inputs are the features rounded to BF16:
+ *   h1 = bf16(relu(W1 x + b1)), h2 = bf16(relu(W2 h1 + b2)), z = W3 . h2 + b3.
+ * Training loss: mean over edges of w * BCE(sigmoid(z), y), w = pos_weight for
+ * y = 1 and 1 for y = 0; labels y are 1 for candidate edges of a given tour.
+ * ------------------------------------------------------------------------ */
+#define ACO_MLP_PARAMS 4801
+#define ACO_MLP_OFF_W1 0
+#define ACO_MLP_OFF_B1 512
+#define ACO_MLP_OFF_W2 576
+#define ACO_MLP_OFF_B2 4672
+#define ACO_MLP_OFF_W3 4736
+#define ACO_MLP_OFF_B3 4800
+#define ACO_MLP_OUT_LOGIT 0 /* out[e] = z */
+#define ACO_MLP_OUT_ETA_B 1 /* out[e] = sigmoid(z)^beta (FP64, rounded once to FP32) */
+
+/* Bytes of the workspace aco_edge_features needs (an exact integer sum). */
+size_t aco_features_workspace_bytes(void);
+
+/* The 8 features of every candidate edge.
+ *   xy [n][2], nn/nnd [n][k], rev [n][k] as written by aco_build_candidates
+ *   feat  float [n][k][8] (output, 16-byte aligned)
+ * Errors: INVALID_ARG (n < 2, k out of [1, min(n-1, ACO_MAX_K)], NULL
+ * pointer, misaligned feat), WORKSPACE. */
+int aco_edge_features(const int32_t *xy, int32_t n, int32_t k, const int32_t *nn,
+                      const int32_t *nnd, const int8_t *rev, float *feat, void *ws,
+                      size_t ws_bytes, void *stream);
+
+/* Forward pass over E edges (E = n*k when feat comes from aco_edge_features).
+ *   feat  float [E][8] (16-byte aligned); theta float [ACO_MLP_PARAMS]
+ *   out   float [E]: the logit (ACO_MLP_OUT_LOGIT) or, with ACO_MLP_OUT_ETA_B,
+ *         the eta_b table that aco_construct_tours reads (sigmoid(z)^beta).
+ * E = 0 does nothing.  Errors: INVALID_ARG. */
+int aco_mlp_forward(const float *feat, int64_t E, const float *theta, int32_t mode,
+                    double beta, float *out, void *stream);
+
+/* Bytes of the workspace aco_mlp_backward needs for E edges. */
+size_t aco_mlp_backward_workspace_bytes(int64_t E);
+
+/* Gradient of the training loss over E >= 1 edges, with respect to theta
+ * (weights through their BF16 values).  The gradients of the pre-activations
+ * are rounded to BF16 where they enter the weight and input products, as the
+ * matrix cores consume them.  Deterministic: partial sums are added in a
+ * fixed order.
+ *   labels uint8 [E] (0 or 1); pos_weight > 0
+ *   grad  float [ACO_MLP_PARAMS] (output); loss double [1] (output, may be NULL)
+ * Errors: INVALID_ARG, WORKSPACE. */
+int aco_mlp_backward(const float *feat, const uint8_t *labels, int64_t E, const float *theta,
+                     float pos_weight, float *grad, double *loss, void *ws, size_t ws_bytes,
+                     void *stream);
+
+/* One Adam step on the FP32 master parameters (in place), step >= 1:
+ *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
+ *   theta -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
+ *   theta, m, v, grad  float [ACO_MLP_PARAMS]   Errors: INVALID_ARG. */
+int aco_mlp_adam(float *theta, float *m, float *v, const float *grad, int32_t step, float lr,
+                 float beta1, float beta2, float eps, void *stream);
+
+/* Training labels: labels[i][r] = 1 if {i, nn[i][r]} is an edge of the closed
+ * tour (a permutation of 0..n-1), else 0.
+ *   tour int32 [n]; labels uint8 [n][k] (output); pos_ws int32 [n] (scratch)
+ * Errors: INVALID_ARG. */
+int aco_tour_edge_labels(int32_t n, int32_t k, const int32_t *nn, const int32_t *tour,
+                         uint8_t *labels, int32_t *pos_ws, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -35,8 +35,13 @@ EXPORTS = (
     "aco_init_pheromone", "aco_construct_workspace_bytes", "aco_construct_tours",
     "aco_update_workspace_bytes", "aco_update_pheromone", "aco_track_best",
     "aco_run_workspace_bytes", "aco_run", "aco_batch_workspace_bytes", "aco_batch_layout",
-    "aco_batch_setup", "aco_batch_iterate", "aco_run_batched",
+    "aco_batch_setup", "aco_batch_iterate", "aco_run_batched", "aco_features_workspace_bytes",
+    "aco_edge_features", "aco_mlp_forward", "aco_mlp_backward_workspace_bytes",
+    "aco_mlp_backward", "aco_mlp_adam", "aco_tour_edge_labels",
 )
+ACO_MLP_PARAMS = 4801
+ACO_MLP_OUT_LOGIT = 0
+ACO_MLP_OUT_ETA_B = 1
 ACO_VIS_BITS = 1
 ACO_VIS_BYTES = 2
 
@@ -92,6 +97,14 @@ def lib():
                                             i32, p, p, p, p, sz, p]),
             "aco_run_batched": (C.c_int, [p, p, i32, C.POINTER(AcoParams), i32, p, p, p, p, sz,
                                           p, p]),
+            "aco_features_workspace_bytes": (sz, []),
+            "aco_edge_features": (C.c_int, [p, i32, i32, p, p, p, p, p, sz, p]),
+            "aco_mlp_forward": (C.c_int, [p, i64, p, i32, dbl, p, p]),
+            "aco_mlp_backward_workspace_bytes": (sz, [i64]),
+            "aco_mlp_backward": (C.c_int, [p, p, i64, p, C.c_float, p, p, p, sz, p]),
+            "aco_mlp_adam": (C.c_int, [p, p, p, p, i32, C.c_float, C.c_float, C.c_float,
+                                       C.c_float, p]),
+            "aco_tour_edge_labels": (C.c_int, [i32, i32, p, p, p, p, p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -213,6 +226,56 @@ def aco_run(xy, n, params: AcoParams, best_tour, best_len, iter_best, tau_out, w
         _stream(stream)))
 
 
+# ------------------------------------------------------------ learned heuristic
+def aco_features_workspace_bytes() -> int:
+    return int(lib().aco_features_workspace_bytes())
+
+
+def aco_edge_features(xy, n, k, nn, nnd, rev, feat, ws, stream=None):
+    torch = _t()
+    _check(lib().aco_edge_features(
+        _ptr(xy, torch.int32, "xy"), n, k, _ptr(nn, torch.int32, "nn"),
+        _ptr(nnd, torch.int32, "nnd"), _ptr(rev, torch.int8, "rev"),
+        _ptr(feat, torch.float32, "feat"), _ptr(ws, torch.uint8, "ws"), ws.numel(),
+        _stream(stream)))
+
+
+def aco_mlp_forward(feat, E, theta, mode, beta, out, stream=None):
+    torch = _t()
+    _check(lib().aco_mlp_forward(
+        _ptr(feat, torch.float32, "feat"), int(E), _ptr(theta, torch.float32, "theta"), int(mode),
+        float(beta), _ptr(out, torch.float32, "out"), _stream(stream)))
+
+
+def aco_mlp_backward_workspace_bytes(E: int) -> int:
+    return int(lib().aco_mlp_backward_workspace_bytes(int(E)))
+
+
+def aco_mlp_backward(feat, labels, E, theta, pos_weight, grad, loss, ws, stream=None):
+    torch = _t()
+    _check(lib().aco_mlp_backward(
+        _ptr(feat, torch.float32, "feat"), _ptr(labels, torch.uint8, "labels"), int(E),
+        _ptr(theta, torch.float32, "theta"), float(pos_weight), _ptr(grad, torch.float32, "grad"),
+        _ptr(loss, torch.float64, "loss"), _ptr(ws, torch.uint8, "ws"), ws.numel(),
+        _stream(stream)))
+
+
+def aco_mlp_adam(theta, m, v, grad, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    torch = _t()
+    f32 = torch.float32
+    _check(lib().aco_mlp_adam(
+        _ptr(theta, f32, "theta"), _ptr(m, f32, "m"), _ptr(v, f32, "v"), _ptr(grad, f32, "grad"),
+        int(step), float(lr), float(beta1), float(beta2), float(eps), _stream(stream)))
+
+
+def aco_tour_edge_labels(n, k, nn, tour, labels, pos_ws, stream=None):
+    torch = _t()
+    _check(lib().aco_tour_edge_labels(
+        n, k, _ptr(nn, torch.int32, "nn"), _ptr(tour, torch.int32, "tour"),
+        _ptr(labels, torch.uint8, "labels"), _ptr(pos_ws, torch.int32, "pos_ws"),
+        _stream(stream)))
+
+
 # ------------------------------------------------------------ convenience holder
 @dataclass
 class Colony:
@@ -228,6 +291,7 @@ class Colony:
     seed: int = 1
     deposit_shift: int = 32
     eta: object = None          # optional learned heuristic score, float32 [n, k] on GPU
+    theta: object = None        # optional MLP parameters (float32 [ACO_MLP_PARAMS] on GPU)
     want_prob: bool = False
     device: str = "cuda"
 
@@ -259,6 +323,22 @@ class Colony:
     def build_candidates(self, stream=None):
         aco_build_candidates(self.xy, self.n, self.k, self.beta, self.eta, self.nn, self.nnd,
                              self.rev, self.eta_b, self.grid, stream)
+        if self.theta is not None:
+            self.apply_learned_heuristic(self.theta, stream)
+
+    def features(self, stream=None):
+        """The 8 edge features [n, k, 8] (float32, GPU)."""
+        torch = _t()
+        feat = torch.empty((self.n, self.k, 8), dtype=torch.float32, device=self.device)
+        ws = torch.empty(aco_features_workspace_bytes(), dtype=torch.uint8, device=self.device)
+        aco_edge_features(self.xy, self.n, self.k, self.nn, self.nnd, self.rev, feat, ws, stream)
+        return feat
+
+    def apply_learned_heuristic(self, theta, stream=None):
+        """Replace eta_b by sigmoid(MLP score)^beta (candidates must be built)."""
+        feat = self.features(stream)
+        aco_mlp_forward(feat, self.n * self.k, theta, ACO_MLP_OUT_ETA_B, self.beta, self.eta_b,
+                        stream)
 
     def init_pheromone(self, stream=None):
         self.tau0, self.L_nn = aco_init_pheromone(self.xy, self.n, self.k, self.nn, self.nnd,

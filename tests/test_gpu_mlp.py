@@ -1,0 +1,304 @@
+"""GPU parity of the learned edge heuristic (features, MLP forward, backward,
+Adam, labels) against its CPU oracle, and colony construction with a learned
+eta table.
+
+Tolerances follow from the arithmetic.  Features are exactly rounded FP64
+expressions on both sides: bit-exact.  The network: both sides use the same
+BF16 operands and differ only in the order of FP32 accumulation, bounded per
+edge by the oracle's forward_bound (FP32 sum error, plus the propagated
+effect of a hidden value that may round to the other BF16 neighbour).  On
+dyadic inputs every sum is exact and the logits must agree bit for bit.
+Gradients: a term of a gradient sum differs only where a BF16 rounding of d2
+or d1 falls the other way (one BF16 step, 2^-8 relative), so
+|dgrad_p| <= 2^-8 * S_p, S_p = sum of |term| (the oracle's backward_scale);
+edges where a forward rounding or ReLU may flip add up to twice their own
+scale."""
+import numpy as np
+import pytest
+
+import oracle as orc
+from oracle import mlp as omlp
+from paper_1709_03187_amd import instances
+from tests.gpu_util import check_tours, colony, require_gpu, say, threads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _aco():
+    import paper_1709_03187_amd as aco
+    return aco
+
+
+def _dev(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a)).cuda()
+
+
+def _np(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+# ------------------------------------------------------------------ features
+def _feature_case(name):
+    if name == "c1":
+        return instances.make_coords("c1"), 10
+    if name == "c2":
+        return instances.make_coords("c2"), 16
+    if name == "five":
+        return np.array([[0, 0], [3, 4], [-6, -8], [20, 0], [0, 30]], np.int32), 3
+    if name == "clustered":       # many coincident points: d = 0 rows
+        return instances.clustered_coords(3000, 11, clusters=7, sigma=3.0), 16
+    if name == "k1":
+        return instances.uniform_coords(50, 12), 1
+    if name == "symmetric":       # city 0's candidate offsets sum to zero
+        return np.array([[0, 0], [10, 0], [-10, 0], [0, 10], [0, -10], [500, 500], [-700, 300]],
+                        np.int32), 4
+    if name == "wide":            # coordinates near the limit
+        return instances.uniform_coords(2000, 13, hi=2**29 - 1), 12
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("case", ["five", "symmetric", "k1", "c1", "clustered", "wide", "c2"])
+def test_edge_features_bit_exact(case):
+    xy, k = _feature_case(case)
+    say(f"[mlp] features {case} n={len(xy)} k={k}")
+    col = colony(xy, k, 4)
+    col.build_candidates()
+    f = _np(col.features())
+    nn, nnd = orc.knn_rows(xy, k, threads=threads())
+    np.testing.assert_array_equal(_np(col.nn), nn)
+    fo = omlp.features(xy, nn, nnd, orc.rev(nn))
+    bad = np.nonzero(f.view(np.uint32) != fo.view(np.uint32))
+    assert bad[0].size == 0, (case, bad[0][:5], bad[1][:5], bad[2][:5],
+                              f[bad][:5], fo[bad][:5])
+    if case == "symmetric":
+        assert f[0, 0, 4] == 1.0 and f[0, 0, 5] == 0.0
+
+
+# ------------------------------------------------------------------ forward
+def _forward_gpu(theta, X, mode, beta=2.0):
+    import torch
+    aco = _aco()
+    E = len(X)
+    out = torch.full((max(E, 1),), np.nan, dtype=torch.float32, device="cuda")
+    feat = _dev(X.reshape(-1, 8)) if E else torch.empty((1, 8), dtype=torch.float32,
+                                                        device="cuda")
+    aco.aco_mlp_forward(feat, E, _dev(theta), mode, beta, out)
+    return _np(out)[:E]
+
+
+def _assert_exact_preconditions(theta, X):
+    """Every partial sum of the dyadic network fits FP32 exactly: magnitudes
+    below 2^24 units of the grid each layer's products live on."""
+    z, c = omlp.forward(theta, X, True, want_cache=True)
+    Sz = np.abs(c["h2b"]) @ np.abs(c["W3"]) + abs(c["b3"])
+    assert c["s1"].max() < 2.0**(24 - 7) and c["s2"].max() < 2.0**(24 - 10)
+    assert Sz.max() < 2.0**(24 - 13)
+    return z
+
+
+@pytest.mark.parametrize("E", [1, 17, 100003])
+def test_mlp_forward_dyadic_bit_exact(E):
+    aco = _aco()
+    theta, X, _ = instances.mlp_dyadic_batch(E, 40 + E)
+    z = _assert_exact_preconditions(theta, X)
+    zg = _forward_gpu(theta, X, aco.ACO_MLP_OUT_LOGIT)
+    np.testing.assert_array_equal(zg.astype(np.float64), z)
+
+
+@pytest.mark.parametrize("E", [1, 15, 16, 17, 1000, 16 * 4096 * 2 + 5])
+def test_mlp_forward_logits(E):
+    aco = _aco()
+    theta = instances.mlp_parameters(E)
+    X, _ = instances.mlp_edge_batch(E, 100 + E)
+    zg = _forward_gpu(theta, X, aco.ACO_MLP_OUT_LOGIT)
+    z, dz, flip = omlp.forward_bound(theta, X)
+    err = np.abs(zg.astype(np.float64) - z)
+    say(f"[mlp] forward E={E}: flip-possible edges {flip.mean():.3f}, "
+        f"max err/bound {np.max(err / dz):.3g}, median err {np.median(err):.3g}")
+    assert (err <= dz).all(), (np.nonzero(err > dz)[0][:5], err[err > dz][:5])
+
+
+@pytest.mark.parametrize("beta", [0.0, 0.5, 2.0, 5.0])
+def test_mlp_forward_eta_table(beta):
+    aco = _aco()
+    E = 20011
+    theta = instances.mlp_parameters(7)
+    X, _ = instances.mlp_edge_batch(E, 8)
+    eb = _forward_gpu(theta, X, aco.ACO_MLP_OUT_ETA_B, beta)
+    if beta == 0.0:
+        assert (eb == 1.0).all()
+        return
+    assert (rel_err_eta(eb, theta, X, beta) <= 1.0).all()
+
+
+def rel_err_eta(eb, theta, X, beta):
+    """|eta_b - sigma(z)^beta| / sigma(z)^beta over its bound: the logit bound
+    times d(log sigma^beta)/dz = beta (1 - sigma) (with the bound's own
+    curvature), plus the FP32 rounding of the table."""
+    z, dz, _ = omlp.forward_bound(theta, X)
+    ref = omlp.sigmoid(z) ** beta
+    rtol = np.expm1(beta * dz) + 2.0**-23
+    return np.abs(eb.astype(np.float64) - ref) / ref / rtol
+
+
+def test_mlp_forward_rejects_bad_arguments():
+    aco = _aco()
+    import torch
+    theta = _dev(instances.mlp_parameters(1))
+    feat = torch.zeros((4, 8), dtype=torch.float32, device="cuda")
+    out = torch.zeros(4, dtype=torch.float32, device="cuda")
+    with pytest.raises(aco.AcoError) as e:
+        aco.aco_mlp_forward(feat, 4, theta, 7, 1.0, out)
+    assert e.value.code == aco.ACO_ERR_INVALID_ARG
+    with pytest.raises(aco.AcoError):
+        aco.aco_mlp_forward(feat, -1, theta, 0, 1.0, out)
+    with pytest.raises(aco.AcoError):       # misaligned features
+        aco.aco_mlp_forward(feat.view(-1)[1:9].view(1, 8), 1, theta, 0, 1.0, out)
+
+
+# ------------------------------------------------------------------ backward
+def _backward_gpu(theta, X, y, pos_weight):
+    import torch
+    aco = _aco()
+    E = len(X)
+    grad = torch.full((aco.ACO_MLP_PARAMS,), np.nan, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ws = torch.empty(aco.aco_mlp_backward_workspace_bytes(E), dtype=torch.uint8, device="cuda")
+    aco.aco_mlp_backward(_dev(X), _dev(y), E, _dev(theta), pos_weight, grad, loss, ws)
+    return _np(grad), float(_np(loss)[0])
+
+
+@pytest.mark.parametrize("kind", ["dyadic", "real"])
+@pytest.mark.parametrize("E,pos_weight", [(1, 1.0), (17, 2.0), (5000, 3.0), (131077, 6.0)])
+def test_mlp_backward_gradient(E, pos_weight, kind):
+    if kind == "dyadic":
+        theta, X, y = instances.mlp_dyadic_batch(E, 300 + E)
+        _assert_exact_preconditions(theta, X)
+        flip = np.zeros(E, bool)
+    else:
+        theta = instances.mlp_parameters(E + 1)
+        X, y = instances.mlp_edge_batch(E, 200 + E)
+        flip = omlp.forward_bound(theta, X)[2]
+    say(f"[mlp] backward {kind} E={E}")
+    g, L = _backward_gpu(theta, X, y, pos_weight)
+    Lo, go = omlp.backward(theta, X, y, pos_weight, True)
+    S = omlp.backward_scale(theta, X, y, pos_weight)
+    tol = 2.0**-8 * S + 1e-30
+    if flip.any():
+        tol = tol + 2.0 * omlp.backward_scale(theta, X[flip], y[flip], pos_weight) * (
+            flip.sum() / E)
+    err = np.abs(g.astype(np.float64) - go)
+    assert np.isfinite(g).all()
+    agg = np.linalg.norm(err) / np.linalg.norm(S)
+    say(f"[mlp] backward {kind} E={E}: flip edges {flip.mean():.3f}, max err/tol "
+        f"{np.max(err / tol):.3g}, aggregate err/|S| {agg:.3g}")
+    assert (err <= tol).all(), np.max(err / tol)
+    assert abs(L - Lo) <= 1e-6 * abs(Lo)
+    g2, L2 = _backward_gpu(theta, X, y, pos_weight)     # deterministic
+    assert np.array_equal(g.view(np.uint32), g2.view(np.uint32)) and L == L2
+
+
+def test_mlp_backward_rejects_bad_arguments():
+    import torch
+    aco = _aco()
+    theta = _dev(instances.mlp_parameters(1))
+    feat = torch.zeros((4, 8), dtype=torch.float32, device="cuda")
+    lab = torch.zeros(4, dtype=torch.uint8, device="cuda")
+    grad = torch.zeros(aco.ACO_MLP_PARAMS, dtype=torch.float32, device="cuda")
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(aco.AcoError) as e:
+        aco.aco_mlp_backward(feat, lab, 4, theta, 1.0, grad, None, small)
+    assert e.value.code == aco.ACO_ERR_WORKSPACE
+    ws = torch.empty(aco.aco_mlp_backward_workspace_bytes(4), dtype=torch.uint8, device="cuda")
+    with pytest.raises(aco.AcoError) as e:
+        aco.aco_mlp_backward(feat, lab, 0, theta, 1.0, grad, None, ws)
+    assert e.value.code == aco.ACO_ERR_INVALID_ARG
+    with pytest.raises(aco.AcoError):
+        aco.aco_mlp_backward(feat, lab, 4, theta, -1.0, grad, None, ws)
+
+
+# ------------------------------------------------------------------ Adam, labels
+def test_adam_step_matches_oracle():
+    import torch
+    aco = _aco()
+    rng = np.random.default_rng(3)
+    P = aco.ACO_MLP_PARAMS
+    t = rng.normal(0, 1, P).astype(np.float32)
+    m = np.zeros(P, np.float32)
+    v = np.zeros(P, np.float32)
+    tg, mg, vg = _dev(t), _dev(m), _dev(v)
+    for step in range(1, 4):
+        g = rng.normal(0, 1e-2, P).astype(np.float32)
+        aco.aco_mlp_adam(tg, mg, vg, _dev(g), step, 2e-3, 0.9, 0.999, 1e-8)
+        t, m, v = omlp.adam_step(t, m, v, g, step, 2e-3, 0.9, 0.999, 1e-8)
+        for a, b in ((tg, t), (mg, m), (vg, v)):
+            np.testing.assert_allclose(_np(a), b, rtol=3e-7, atol=0)
+
+
+def test_tour_edge_labels_bit_exact():
+    import torch
+    aco = _aco()
+    xy = instances.make_coords("c1")
+    k = 10
+    col = colony(xy, k, 4)
+    col.build_candidates()
+    nn, _ = orc.knn_rows(xy, k, threads=threads())
+    np.testing.assert_array_equal(_np(col.nn), nn)
+    for seed in range(3):
+        tour = np.random.default_rng(seed).permutation(len(xy)).astype(np.int32)
+        if seed == 2:
+            tour, _ = orc.nn_tour(xy, *orc.knn_rows(xy, k))
+        lab = torch.empty((len(xy), k), dtype=torch.uint8, device="cuda")
+        pos = torch.empty(len(xy), dtype=torch.int32, device="cuda")
+        aco.aco_tour_edge_labels(len(xy), k, col.nn, _dev(tour.astype(np.int32)), lab, pos)
+        np.testing.assert_array_equal(_np(lab), omlp.labels_from_tour(nn, tour))
+
+
+# ------------------------------------------------------------------ colony use
+def test_learned_eta_table_in_colony():
+    """Colony(theta): features then forward write eta_b; checked against the
+    oracle's FP64 network on the oracle's own features."""
+    xy = instances.make_coords("c1")
+    k, beta = 10, 2.0
+    theta = instances.mlp_parameters(21)
+    col = colony(xy, k, 8, beta=beta, theta=_dev(theta))
+    col.build_candidates()
+    eb = _np(col.eta_b).reshape(-1)
+    nn, nnd = orc.knn_rows(xy, k, threads=threads())
+    X = omlp.features(xy, nn, nnd, orc.rev(nn)).reshape(-1, 8)
+    assert (rel_err_eta(eb, theta, X, beta) <= 1.0).all()
+
+
+def test_construction_with_learned_eta_table():
+    """The colony's construction and update with an eta table given by the
+    oracle's network: the standard replay protocol (probabilities to 1e-5,
+    choices equal outside the 1e-6 window, bit-exact update)."""
+    import torch
+    xy = instances.make_coords("c1")
+    k, m, beta, seed = 10, 32, 2.0, 5
+    nn, nnd = orc.knn_rows(xy, k, threads=threads())
+    X = omlp.features(xy, nn, nnd, orc.rev(nn)).reshape(-1, 8)
+    eta32 = omlp.sigmoid(omlp.forward(instances.mlp_parameters(22), X, True)).astype(
+        np.float32).reshape(len(xy), k)
+    col = colony(xy, k, m, beta=beta, seed=seed, eta=_dev(eta32), want_prob=True)
+    col.setup()
+    eta = eta32.astype(np.float64)
+    np.testing.assert_allclose(_np(col.eta_b), (eta ** beta).astype(np.float32), rtol=1.2e-7)
+    tau = _np(col.tau).copy()
+    for it in range(2):
+        col.construct(it)
+        col.update()
+        torch.cuda.synchronize()
+        tours, lengths, slots = _np(col.tours), _np(col.lengths), _np(col.slots)
+        check_tours(xy, nn, nnd, tau, 1.0, beta, seed, it, tours, lengths, slots,
+                    _np(col.step_prob), np.arange(m), eta=eta, label=f"learned it={it}")
+        tau = orc.update(nn, tau, tours, lengths, 0.1, 32)
+        np.testing.assert_array_equal(_np(col.tau), tau)
