@@ -46,6 +46,7 @@ def construct_bytes_per_launch(n: int, m: int, k: int) -> int:
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_construct_c3_n200k_m1024_k16.md")
 TRAFFIC_SOURCES = ["paper_1709_03187_amd/csrc/construct.hip",
+                   "paper_1709_03187_amd/csrc/colony.hpp",
                    "paper_1709_03187_amd/csrc/device.hpp",
                    "paper_1709_03187_amd/csrc/common.hpp"]
 
@@ -140,6 +141,120 @@ def batched_block():
             "mean_best_len": float(L0.mean())}
 
 
+MLP_FLOP_FORWARD = 2 * (8 * 64 + 64 * 64 + 64)          # per edge: three layers
+MLP_FLOP_BACKWARD = MLP_FLOP_FORWARD + 2 * (64 + 64 * 64 + 64 * 64 + 64 * 8)  # + dW3, d1, dW2, dW1
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def _timed(fn, reps):
+    """Mean milliseconds of fn() over reps launches, HIP events on the current stream."""
+    import torch
+    stream = torch.cuda.current_stream()
+    fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def _colony_until(xy, cfg, beta, budget_s, iterations, theta=None):
+    """Best length of a colony run within budget_s seconds (set-up included)."""
+    import torch
+
+    import paper_1709_03187_amd as aco
+    col = aco.Colony(xy=xy, k=cfg["k"], m=cfg["m"], alpha=cfg["alpha"], beta=beta,
+                     rho=cfg["rho"], seed=cfg["seed"], theta=theta)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    col.setup()
+    torch.cuda.synchronize()
+    setup = time.time() - t0
+    it = 0
+    while it < iterations:
+        t_it = time.time()
+        col.iterate(it)
+        torch.cuda.synchronize()
+        it += 1
+        # stop where one more iteration (as long as the last) would pass the budget
+        if budget_s is not None and time.time() + (time.time() - t_it) > t0 + budget_s:
+            break
+    res = dict(best_len=int(col.best_len.item()), iterations=it, seconds=time.time() - t0,
+               setup_s=setup, L_nn=col.L_nn)
+    del col
+    torch.cuda.empty_cache()
+    return res
+
+
+def learned_block(xy_eval, cfg):
+    """Learned heuristic: 64 uniform n=20,000 instances (seeds 1000..1063) are
+    solved by the batched colonies (m=64, k=16, 30 iterations, beta=2); the
+    candidate edges of their best tours are the positive labels.  3,000 Adam
+    steps of 65,536 edges train the network.  Then the evaluation workload
+    runs with plain eta (beta=2, its 20 iterations: wall clock T) and with the
+    learned score (beta=8, chosen on held-out uniform instances) for the same
+    T, set-up included; plain eta at beta=8 is reported beside it."""
+    import torch
+
+    import paper_1709_03187_amd as aco
+    from paper_1709_03187_amd import instances, learned
+
+    k = cfg["k"]
+    xys = [instances.uniform_coords(20000, 1000 + b) for b in range(64)]
+    data = learned.training_set(xys, k=k, m=64, iterations=30, seed=1)
+    E = int(data.feat.shape[0])
+    set_s = data.seconds
+    tr = learned.train(data, instances.mlp_parameters(0), steps=3000, batch=65536, lr=2e-3,
+                       log_every=1000)
+    theta = tr.theta
+    # kernel rates: backward on one training batch, forward on the evaluation edges
+    B = 65536
+    grad = torch.empty(aco.ACO_MLP_PARAMS, dtype=torch.float32, device="cuda")
+    ws = torch.empty(aco.aco_mlp_backward_workspace_bytes(B), dtype=torch.uint8, device="cuda")
+    bwd_ms = _timed(lambda: aco.aco_mlp_backward(data.feat[:B], data.labels[:B], B, theta, 1.0,
+                                                 grad, None, ws), 50)
+    del data, ws
+    col = aco.Colony(xy=xy_eval, k=k, m=8, beta=8.0)
+    col.build_candidates()
+    feat = col.features()
+    Ev = col.n * k
+    fwd_ms = _timed(lambda: aco.aco_mlp_forward(feat, Ev, theta, aco.ACO_MLP_OUT_ETA_B, 8.0,
+                                                col.eta_b), 50)
+    fws = torch.empty(aco.aco_features_workspace_bytes(), dtype=torch.uint8, device="cuda")
+    feat_ms = _timed(lambda: aco.aco_edge_features(col.xy, col.n, k, col.nn, col.nnd, col.rev,
+                                                   feat, fws), 20)
+    del col, feat
+    torch.cuda.empty_cache()
+    its = cfg["iterations"]
+    plain = _colony_until(xy_eval, cfg, cfg["beta"], None, its)
+    T = plain["seconds"]
+    lrn = _colony_until(xy_eval, cfg, 8.0, T, 100 * its, theta=theta)
+    plain8 = _colony_until(xy_eval, cfg, 8.0, T, 100 * its)
+    fwd_tflops = MLP_FLOP_FORWARD * Ev / (fwd_ms * 1e-3) / 1e12
+    bwd_tflops = MLP_FLOP_BACKWARD * B / (bwd_ms * 1e-3) / 1e12
+    return {
+        "training": {"instances": 64, "n": 20000, "edges": E,
+                     "label_colony": "batched, m=64, k=16, beta=2, 30 iterations",
+                     "set_build_s": set_s,
+                     "steps": 3000, "batch": 65536, "lr": 2e-3, "train_s": tr.seconds,
+                     "loss": [[s_, l_] for s_, l_ in tr.losses]},
+        "kernels": {
+            "mlp_forward": {"edges": Ev, "ms": fwd_ms, "flop_per_edge": MLP_FLOP_FORWARD,
+                            "tflops": fwd_tflops, "peak_bf16_tflops": MFMA_BF16_PEAK_TFLOPS,
+                            "frac": fwd_tflops / MFMA_BF16_PEAK_TFLOPS},
+            "mlp_backward": {"edges": B, "ms": bwd_ms, "flop_per_edge": MLP_FLOP_BACKWARD,
+                             "tflops": bwd_tflops, "frac": bwd_tflops / MFMA_BF16_PEAK_TFLOPS},
+            "edge_features": {"edges": Ev, "ms": feat_ms}},
+        "equal_wall_clock": {
+            "seconds": T, "plain_beta2": plain, "learned_beta8": lrn, "plain_beta8": plain8,
+            "gain_vs_plain": (plain["best_len"] - lrn["best_len"]) / plain["best_len"],
+            "gain_vs_plain_same_beta": (plain8["best_len"] - lrn["best_len"]) / plain8["best_len"]},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,6 +263,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -266,11 +382,14 @@ def main():
         "best_len": best_len,
     }
     tau0_gpu = col.tau0
+    del col
+    torch.cuda.empty_cache()
     if not args.no_batched:
         log("[bench] batched workload")
-        del col
-        torch.cuda.empty_cache()
         out["batched"] = batched_block()
+    if not args.no_learned:
+        log("[bench] learned heuristic: training and equal-time comparison")
+        out["learned"] = learned_block(xy, cfg)
     if not args.no_cpu_baseline:
         threads = args.cpu_threads or max(1, min(16, os.cpu_count() or 1))
         log(f"[bench] cpu baseline with {threads} threads")
