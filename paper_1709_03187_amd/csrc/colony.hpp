@@ -90,83 +90,93 @@ struct AntTask {
 // Builds one ant's tour with the whole wave (Section 2, Eq. 1).  Lane r < k
 // holds candidate r of the current city.  The critical path of a step is:
 // row load -> visited test (LDS) -> DPP scan -> ballot -> next row address.
-// (Touching the candidates' rows ahead of time does not help: vector loads
-// complete in order, so the next row load would wait for the slowest touch.)
+// (Touching or loading the candidates' rows ahead of time does not help: the
+// extra loads and lane shuffles cost more than the hidden latency.)  Steps run
+// in blocks of 64: one Philox call gives the block's 64 words (lane l: step
+// base + l) and the block's outputs are staged in lanes and stored together,
+// so the inner loop holds only the step itself.
 // KP is the scan width, the smallest power of two >= k.  `grid()` returns the
-// instance's GridView (only needed on a fallback step).
-template <int KP, class Vis, class GridFn>
-__device__ void build_ant(const AntTask &T, const Vis &vis, const GridFn &grid)
+// instance's GridView (used by fallback steps).
+template <int KP, bool kProb, class Vis, class GridFn>
+__device__ void build_ant_impl(const AntTask &T, const Vis &vis, const GridFn &grid)
 {
     const int lane = lane_id();
     const int32_t n = T.n, k = T.k;
     vis.clear(n, lane);
     auto visited = [&](int city) { return vis.test(city); };
-    const bool want_prob = T.prob != nullptr;
 
-    // lane l holds the Philox word of step (base + l)
     uint32_t rnd = colony_draw(T.seed, T.iteration, T.ant, (uint32_t)lane);
     const uint32_t x0 = (uint32_t)read_lane_i32((int32_t)rnd, 0);
     const int32_t start = (int32_t)(((uint64_t)x0 * (uint64_t)n) >> 32);
     if (lane == 0) vis.set(start);
 
-    int32_t st_city = start;      // staged outputs: lane l holds step (base + l)
-    uint32_t st_slot = kNoSlot;
-    float st_prob = 1.0f;
-    int32_t c = start;
     const bool active = lane < k;
     const int lr = active ? lane : k - 1;   // idle lanes re-read a valid element
-    GridView g;
-    bool have_grid = false;
+    const GridView g = grid();              // read once: no state carried through the loop
+    int32_t c = start;
 
-    for (int32_t step = 1; step < n; ++step) {
-        if ((step & 63) == 0)
-            rnd = colony_draw(T.seed, T.iteration, T.ant, (uint32_t)(step + lane));
-        const CandW e = T.rows[(int64_t)c * k + lr];
-        const int32_t j = e.city;
-        const uint32_t seen = visited(j);          // every lane reads a valid word
-        const bool unv = active && seen == 0u;
-        const double wv = (unv && e.w > 0.0f) ? (double)e.w : 0.0;
-        const double cum = wave_incl_scan_f64(wv, KP);
-        const double S = read_lane_f64(cum, k - 1);
-        int32_t jn;
-        uint32_t slot;
-        float prob = -1.0f;
-        if (S > 0.0) {
-            const uint32_t x = (uint32_t)read_lane_i32((int32_t)rnd, step & 63);
-            const double target = (double)x * 0x1p-32 * S;
-            const uint64_t hit = __ballot(wv > 0.0 && target < cum);
-            const int f = hit ? __ffsll((unsigned long long)hit) - 1
-                              : 63 - __clzll((long long)__ballot(wv > 0.0));
-            jn = read_lane_i32(j, f);
-            slot = (uint32_t)f;
-            if (want_prob) prob = (float)(read_lane_f64(wv, f) / S);
-        } else {
-            if (!have_grid) {
-                g = grid();
-                have_grid = true;
+    for (int32_t base = 0; base < n; base += kWave) {
+        if (base > 0) rnd = colony_draw(T.seed, T.iteration, T.ant, (uint32_t)(base + lane));
+        // staged outputs: lane l holds step base + l (step 0 is the start city)
+        int32_t st_city = start;
+        uint32_t st_slot = kNoSlot;
+        float st_prob = 1.0f;
+        const int32_t last = min(base + kWave - 1, n - 1);
+        for (int32_t step = max(base, 1); step <= last; ++step) {
+            const int idx = step - base;
+            const CandW e = T.rows[(int64_t)c * k + lr];
+            const int32_t j = e.city;
+            const uint32_t seen = visited(j);          // every lane reads a valid word
+            const bool unv = active && seen == 0u;
+            const bool live = unv && e.w > 0.0f;
+            const double wv = live ? (double)e.w : 0.0;
+            const double cum = wave_incl_scan_f64(wv, KP);
+            const double S = read_lane_f64(cum, k - 1);
+            int32_t jn;
+            uint32_t slot;
+            float prob = -1.0f;
+            if (S > 0.0) {
+                const uint32_t x = (uint32_t)read_lane_i32((int32_t)rnd, idx);
+                const double target = (double)x * 0x1p-32 * S;
+                const uint64_t any = __builtin_amdgcn_ballot_w64(live);
+                const uint64_t hit = __builtin_amdgcn_ballot_w64(live && target < cum);
+                // first slot whose running sum passes the target; if rounding
+                // leaves none, the last slot that can be chosen
+                const int f = hit ? __ffsll((unsigned long long)hit) - 1
+                                  : 63 - __clzll((long long)any);
+                jn = read_lane_i32(j, f);
+                slot = (uint32_t)f;
+                if constexpr (kProb) prob = (float)(read_lane_f64(wv, f) / S);
+            } else {
+                jn = fallback_city(g, T.xy, c, visited);
+                slot = kNoSlot;
             }
-            jn = fallback_city(g, T.xy, c, visited);
-            slot = kNoSlot;
-        }
-        // a city index is always in range here; the clamp only keeps a logic
-        // error from turning into an out-of-bounds access (tests see the tour)
-        jn = ((uint32_t)jn < (uint32_t)n) ? jn : start;
-        if (lane == 0) vis.set(jn);
-        if (lane == (step & 63)) {
-            st_city = jn;
-            st_slot = slot;
-            st_prob = prob;
-        }
-        if ((step & 63) == 63 || step == n - 1) {
-            const int32_t base = step & ~63;
-            if (base + lane <= step) {
-                T.tour[base + lane] = st_city;
-                T.slots[base + lane] = (uint8_t)st_slot;
-                if (want_prob) T.prob[base + lane] = st_prob;
+            // a city index is always in range here; the clamp only keeps a logic
+            // error from turning into an out-of-bounds access (tests see the tour)
+            jn = ((uint32_t)jn < (uint32_t)n) ? jn : start;
+            if (lane == 0) vis.set(jn);
+            if (lane == idx) {
+                st_city = jn;
+                st_slot = slot;
+                if constexpr (kProb) st_prob = prob;
             }
+            c = jn;
         }
-        c = jn;
+        if (base + lane <= last) {
+            T.tour[base + lane] = st_city;
+            T.slots[base + lane] = (uint8_t)st_slot;
+            if constexpr (kProb) T.prob[base + lane] = st_prob;
+        }
     }
+}
+
+template <int KP, class Vis, class GridFn>
+__device__ void build_ant(const AntTask &T, const Vis &vis, const GridFn &grid)
+{
+    if (T.prob)
+        build_ant_impl<KP, true>(T, vis, grid);
+    else
+        build_ant_impl<KP, false>(T, vis, grid);
 }
 
 // The kx nearest cities of city `me` in (d, index) order, by one thread:

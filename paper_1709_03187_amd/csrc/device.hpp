@@ -300,25 +300,45 @@ __device__ __forceinline__ bool block_slot(const GridHdr &h, int gx, int gy, int
     return row >= 0 && row < h.gh && xa <= xb;
 }
 
+// Largest block radius rho (in cells, around the cell of the point) whose
+// cities are all closer than d_lo, or -1.  A city in the block of radius rho
+// differs from the point by less than (rho + 1) cell in x and in y, so its
+// s = dx^2 + dy^2 < 2 ((rho + 1) cell)^2; with 8 ((rho + 1) cell)^2 <=
+// (2 d_lo - 1)^2 its rounded distance nint(sqrt(s)) is below d_lo.
+__device__ __forceinline__ int closer_block_radius(const GridHdr &h, int64_t d_lo)
+{
+    if (d_lo <= 0 || d_lo > (1 << 29)) return -1;
+    const int64_t q2 = (2 * d_lo - 1) * (2 * d_lo - 1);
+    const int64_t cell = h.cell;
+    auto fits = [&](int64_t t) { const int64_t e = t * cell; return 8 * e * e <= q2; };
+    int64_t t = (int64_t)((double)(2 * d_lo - 1) / ((double)cell * 2.8284271247461903));
+    while (t > 0 && !fits(t)) --t;
+    while (fits(t + 1)) ++t;
+    const int64_t lim = (int64_t)(h.gw > h.gh ? h.gw : h.gh);
+    return (int)((t < lim ? t : lim) - 1);
+}
+
 // Nearest unvisited city to (cx, cy) by key (d, city), searched by the whole
-// wave over square blocks of cells: radius 1 first, then one more ring per
-// pass.  Each pass reads the new cells as contiguous row ranges of `pts`, one
-// city per lane, and keeps a lane-local minimum (the distance is only rounded
-// for cities that can beat it); one wave reduction per pass.  The search stops
-// once every city outside the searched block is provably farther than the
-// best distance found (bound > d_best), so the result is exact.
+// wave over square blocks of cells: radius 1 first (or, given that no
+// unvisited city is closer than d_lo, the first ring outside the block that
+// holds only closer cities), then one more ring per pass.  Each pass reads the
+// new cells as contiguous row ranges of `pts`, one city per lane, and keeps a
+// lane-local minimum (the distance is only rounded for cities that can beat
+// it); one wave reduction per pass.  The search stops once every city outside
+// the searched block is provably farther than the best distance found
+// (bound > d_best), so the result is exact.
 // Returns (d << 32) | city, or ~0 if every city is visited.
 template <class Visited>
 __device__ uint64_t wave_nearest_unvisited(const GridView &g, int32_t cx, int32_t cy,
-                                           const Visited &visited)
+                                           const Visited &visited, int64_t d_lo = 0)
 {
     const GridHdr &h = g.h;
     const int lane = lane_id();
     const int gx = cell_x(h, cx), gy = cell_y(h, cy);
     uint64_t best = ~0ull;
     int64_t s_cut = INT64_MAX;   // cities with s > s_cut cannot beat this lane's best
-    int rin = -1;
-    for (int r = 1;; rin = r, r = r + 1) {
+    int rin = closer_block_radius(h, d_lo);
+    for (int r = rin < 0 ? 1 : rin + 1;; rin = r, r = r + 1) {
         const int nslots = 2 * (2 * r + 1);
         for (int sb = 0; sb < nslots; sb += kWave) {
             const int s = sb + lane;
@@ -374,7 +394,7 @@ __device__ uint64_t wave_nearest_unvisited(const GridView &g, int32_t cx, int32_
 // weight: the first unvisited city of c's extended neighbour table is the
 // nearest unvisited city (the table is in (d, index) order and holds every
 // city closer than its last entry); only when all of them are visited is the
-// grid searched.
+// grid searched, from outside the block that holds only closer cities.
 template <class Visited>
 __device__ int32_t fallback_city(const GridView &g, const int32_t *xy, int32_t c,
                                  const Visited &visited)
@@ -389,8 +409,12 @@ __device__ int32_t fallback_city(const GridView &g, const int32_t *xy, int32_t c
     }
     const uint64_t bal = __ballot(unv);
     if (bal) return read_lane_i32(j, __ffsll((unsigned long long)bal) - 1);
+    // every city closer than the table's last entry is in the table, hence
+    // visited: the answer is at least as far as that entry
     const int32_t cx = xy[2 * (int64_t)c], cy = xy[2 * (int64_t)c + 1];
-    return (int32_t)(uint32_t)wave_nearest_unvisited(g, cx, cy, visited);
+    const int32_t jl = read_lane_i32(j, kx - 1);
+    const int64_t d_lo = nint_sqrt(sq_dist(cx, cy, xy[2 * (int64_t)jl], xy[2 * (int64_t)jl + 1]));
+    return (int32_t)(uint32_t)wave_nearest_unvisited(g, cx, cy, visited, d_lo);
 }
 
 }  // namespace aco
