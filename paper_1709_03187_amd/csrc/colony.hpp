@@ -90,8 +90,10 @@ struct AntTask {
 // Builds one ant's tour with the whole wave (Section 2, Eq. 1).  Lane r < k
 // holds candidate r of the current city.  The critical path of a step is:
 // row load -> visited test (LDS) -> DPP scan -> ballot -> next row address.
-// (Touching or loading the candidates' rows ahead of time does not help: the
-// extra loads and lane shuffles cost more than the hidden latency.)  Steps run
+// The row of the first candidate that can be chosen (the nearest; usually the
+// heaviest) is loaded as soon as the visited test is done, so when the draw
+// picks it the load overlaps the scan.  (Loading all k rows ahead costs more
+// in loads and lane shuffles than the latency it hides.)  Steps run
 // in blocks of 64: one Philox call gives the block's 64 words (lane l: step
 // base + l) and the block's outputs are staged in lanes and stored together,
 // so the inner loop holds only the step itself.
@@ -115,6 +117,7 @@ __device__ void build_ant_impl(const AntTask &T, const Vis &vis, const GridFn &g
     const GridView g = grid();              // read once: no state carried through the loop
     int32_t c = start;
 
+    CandW e = T.rows[(int64_t)c * k + lr];
     for (int32_t base = 0; base < n; base += kWave) {
         if (base > 0) rnd = colony_draw(T.seed, T.iteration, T.ant, (uint32_t)(base + lane));
         // staged outputs: lane l holds step base + l (step 0 is the start city)
@@ -124,11 +127,19 @@ __device__ void build_ant_impl(const AntTask &T, const Vis &vis, const GridFn &g
         const int32_t last = min(base + kWave - 1, n - 1);
         for (int32_t step = max(base, 1); step <= last; ++step) {
             const int idx = step - base;
-            const CandW e = T.rows[(int64_t)c * k + lr];
             const int32_t j = e.city;
             const uint32_t seen = visited(j);          // every lane reads a valid word
             const bool unv = active && seen == 0u;
             const bool live = unv && e.w > 0.0f;
+            const uint64_t any = __builtin_amdgcn_ballot_w64(live);
+            // the first candidate that can be chosen is the likeliest next city
+            // (rows are in distance order): its row is loaded while the scan runs
+            int32_t guess = -1;
+            CandW eg;
+            if (any) {
+                guess = read_lane_i32(j, __ffsll((unsigned long long)any) - 1);
+                eg = T.rows[(int64_t)guess * k + lr];
+            }
             const double wv = live ? (double)e.w : 0.0;
             const double cum = wave_incl_scan_f64(wv, KP);
             const double S = read_lane_f64(cum, k - 1);
@@ -138,7 +149,6 @@ __device__ void build_ant_impl(const AntTask &T, const Vis &vis, const GridFn &g
             if (S > 0.0) {
                 const uint32_t x = (uint32_t)read_lane_i32((int32_t)rnd, idx);
                 const double target = (double)x * 0x1p-32 * S;
-                const uint64_t any = __builtin_amdgcn_ballot_w64(live);
                 const uint64_t hit = __builtin_amdgcn_ballot_w64(live && target < cum);
                 // first slot whose running sum passes the target; if rounding
                 // leaves none, the last slot that can be chosen
@@ -154,6 +164,10 @@ __device__ void build_ant_impl(const AntTask &T, const Vis &vis, const GridFn &g
             // a city index is always in range here; the clamp only keeps a logic
             // error from turning into an out-of-bounds access (tests see the tour)
             jn = ((uint32_t)jn < (uint32_t)n) ? jn : start;
+            if (jn == guess)
+                e = eg;
+            else
+                e = T.rows[(int64_t)jn * k + lr];
             if (lane == 0) vis.set(jn);
             if (lane == idx) {
                 st_city = jn;
