@@ -33,7 +33,7 @@ static_assert(kOffB3 + 1 == kNParam, "parameter block layout");
 
 constexpr int kWaves = 4;               // waves per workgroup of the MLP kernels
 constexpr int kTile = 16;               // edges per wave per step
-constexpr int kBackwardMaxBlocks = 1024;
+constexpr int kBackwardMaxBlocks = 256;   // one workgroup per CU at the kernel's occupancy
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -395,19 +395,35 @@ __global__ __launch_bounds__(256) void k_mlp_backward(const float *feat, const u
     if (threadIdx.x == 0) loss_partial[blockIdx.x] = lred[0];
 }
 
-__global__ void k_mlp_reduce(const float *partial, const double *loss_partial, int blocks,
-                             double inv_e, float *grad, double *loss)
+// Sum of the workgroups' partial rows, 64 parameters per block: thread
+// (q, p) adds rows q, q + 4, q + 8, ... with four interleaved accumulators,
+// then the four quarter sums are added in order q = 0..3.  The order depends
+// only on the number of rows, so results are reproducible.
+__global__ __launch_bounds__(256) void k_mlp_reduce(const float *partial,
+                                                    const double *loss_partial, int blocks,
+                                                    double inv_e, float *grad, double *loss)
 {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ float part[4][64];
+    const int pl = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int p = blockIdx.x * 64 + pl;
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
     if (p < kNParam) {
-        float s = 0.0f;
-        for (int b = 0; b < blocks; ++b) s += partial[(int64_t)b * kNParam + p];
-        grad[p] = s;
+        int b = q;
+        for (; b + 12 < blocks; b += 16) {
+            a0 += partial[(int64_t)b * kNParam + p];
+            a1 += partial[(int64_t)(b + 4) * kNParam + p];
+            a2 += partial[(int64_t)(b + 8) * kNParam + p];
+            a3 += partial[(int64_t)(b + 12) * kNParam + p];
+        }
+        for (; b < blocks; b += 4) a0 += partial[(int64_t)b * kNParam + p];
     }
-    if (p == kNParam && loss) {
-        double s = 0.0;
-        for (int b = 0; b < blocks; ++b) s += loss_partial[b];
-        *loss = s * inv_e;
+    part[q][pl] = (a0 + a1) + (a2 + a3);
+    __syncthreads();
+    if (q == 0 && p < kNParam) grad[p] = ((part[0][pl] + part[1][pl]) + part[2][pl]) + part[3][pl];
+    if (blockIdx.x == 0 && threadIdx.x == 0 && loss) {
+        double t = 0.0;
+        for (int b = 0; b < blocks; ++b) t += loss_partial[b];
+        *loss = t * inv_e;
     }
 }
 
@@ -551,8 +567,8 @@ extern "C" int aco_mlp_backward(const float *feat, const uint8_t *labels, int64_
     hipLaunchKernelGGL(k_mlp_backward, dim3(G), dim3(64 * kWaves), 0, st, feat, labels, E, theta,
                        pos_weight, (float)(1.0 / (double)E), partial, lpart);
     ACO_LAUNCH_CHECK("k_mlp_backward");
-    hipLaunchKernelGGL(k_mlp_reduce, dim3(blocks_for(kNParam + 1, 256)), dim3(256), 0, st,
-                       partial, lpart, G, 1.0 / (double)E, grad, loss);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((kNParam + 63) / 64), dim3(256), 0, st, partial, lpart,
+                       G, 1.0 / (double)E, grad, loss);
     ACO_LAUNCH_CHECK("k_mlp_reduce");
     return ACO_OK;
 }
