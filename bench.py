@@ -10,8 +10,12 @@ Prints one JSON line.  `value` = ant-steps per second over whole iterations,
 m * (n - 1) ant-steps per iteration.  `roofline` prices the construction
 kernel by its algorithmic bytes per ant-step.  `cpu_baseline` times the CPU
 oracle (threads over ants) on a fixed sample of ants of the same workload.
+Two further objects report the batched colonies (4,096 instances, one
+persistent launch, autotuned) and the learned heuristic (training on the GPU,
+kernel rates, and the equal-wall-clock comparison with plain eta).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                    [--no-batched] [--no-learned]
 """
 from __future__ import annotations
 
