@@ -61,6 +61,8 @@ __device__ __forceinline__ GridView batch_grid(const BatchState &S, int b)
     g.pts = S.pts + off;
     g.ext = S.ext + off * kBatchExt;
     g.ext_stride = kBatchExt;
+    g.pinv = nullptr;     // batched colonies work on city indices
+    g.ext_pos = nullptr;
     return g;
 }
 

@@ -104,7 +104,7 @@ __global__ __launch_bounds__(1024) void k_scan_excl(int32_t *v, int32_t *cursor,
 }
 
 __global__ void k_grid_scatter(const int32_t *__restrict__ xy, GridHdr h, int32_t *cursor,
-                               int4 *pts)
+                               int4 *pts, int32_t *pinv)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= h.n) return;
@@ -112,6 +112,7 @@ __global__ void k_grid_scatter(const int32_t *__restrict__ xy, GridHdr h, int32_
     const int c = cell_y(h, y) * h.gw + cell_x(h, x);
     const int pos = atomicAdd(&cursor[c], 1);
     pts[pos] = make_int4(x, y, (int)i, 0);
+    pinv[i] = pos;
 }
 
 // ------------------------------------------------------------------ k-NN build
@@ -135,10 +136,12 @@ __global__ __launch_bounds__(kKnnThreads) void k_knn(void *grid, int32_t k, int3
     uint64_t *L = lists + threadIdx.x;
     const int4 me = g.pts[p];
     knn_city(g, me, kx, L, kKnnThreads);
-    const int64_t row = (int64_t)me.z * k, xrow = (int64_t)me.z * kx;
+    const int64_t row = (int64_t)me.z * k, xrow = (int64_t)me.z * kx, prow = p * kx;
+    int32_t *ext_pos = (int32_t *)g.ext_pos;
     for (int r = 0; r < kx; ++r) {
         const uint64_t key = L[(int64_t)r * kKnnThreads];
         ext[xrow + r] = (int32_t)(uint32_t)key;
+        ext_pos[prow + r] = g.pinv[(uint32_t)key];
         if (r < k) {
             nn[row + r] = (int32_t)(uint32_t)key;
             nnd[row + r] = (int32_t)(key >> 32);
@@ -250,12 +253,13 @@ int build_grid(const int32_t *xy, int32_t n, void *grid, size_t grid_bytes, hipS
     int32_t *cell_start = (int32_t *)(gb + lay.cell_start);
     int32_t *cursor = (int32_t *)(gb + lay.cursor);
     int4 *pts = (int4 *)(gb + lay.pts);
+    int32_t *pinv = (int32_t *)(gb + lay.pinv);
     k_write_hdr<<<1, 64, 0, st>>>(h, grid);
     k_fill_i32<<<min(4096u, blocks_for(h.ncell + 1, 256)), 256, 0, st>>>(cell_start,
                                                                         h.ncell + 1, 0);
     k_grid_count<<<blocks_for(n, 256), 256, 0, st>>>(xy, h, cell_start);
     k_scan_excl<<<1, 1024, 0, st>>>(cell_start, cursor, (int64_t)h.ncell + 1);
-    k_grid_scatter<<<blocks_for(n, 256), 256, 0, st>>>(xy, h, cursor, pts);
+    k_grid_scatter<<<blocks_for(n, 256), 256, 0, st>>>(xy, h, cursor, pts, pinv);
     ACO_LAUNCH_CHECK("grid build");
     return ACO_OK;
 }

@@ -16,10 +16,15 @@ struct CandW {
 // power of two (probabilities are invariant to a per-row factor).  For
 // alpha in {0, 1} the value is the exact product rounded once to FP32 (times
 // 2^E); for other alpha it is exp2(alpha log2 tau + log2 eta_b - row max).
+struct SameCity {
+    __device__ __forceinline__ int32_t operator()(int32_t c) const { return c; }
+};
+
+template <class CityMap = SameCity>
 __device__ __forceinline__ void choice_row(const int32_t *__restrict__ nn,
                                            const float *__restrict__ tau,
                                            const float *__restrict__ eta_b, int k, double alpha,
-                                           CandW *__restrict__ rows)
+                                           CandW *__restrict__ rows, CityMap map = CityMap())
 {
     if (alpha == 1.0 || alpha == 0.0) {
         double mx = 0.0;
@@ -30,7 +35,7 @@ __device__ __forceinline__ void choice_row(const int32_t *__restrict__ nn,
         const int e = (mx > 0.0) ? -ilogb(mx) : 0;
         for (int r = 0; r < k; ++r) {
             const double p = (alpha == 1.0 ? (double)tau[r] : 1.0) * (double)eta_b[r];
-            rows[r] = CandW{nn[r], (float)ldexp(p, e)};
+            rows[r] = CandW{map(nn[r]), (float)ldexp(p, e)};
         }
     } else {
         double mx = -INFINITY;
@@ -42,7 +47,7 @@ __device__ __forceinline__ void choice_row(const int32_t *__restrict__ nn,
         for (int r = 0; r < k; ++r) {
             const double t = (double)tau[r], eb = (double)eta_b[r];
             const double lw = (t > 0.0 && eb > 0.0) ? alpha * log2(t) + log2(eb) : -INFINITY;
-            rows[r] = CandW{nn[r], (float)((mx > -INFINITY) ? exp2(lw - mx) : 0.0)};
+            rows[r] = CandW{map(nn[r]), (float)((mx > -INFINITY) ? exp2(lw - mx) : 0.0)};
         }
     }
 }
@@ -75,9 +80,41 @@ struct VisBytes {
     }
 };
 
+// How an ant names cities.  By index: the batched colonies.  By position in
+// the grid's cell order: the single-instance construction, whose candidate
+// rows, 64-NN table and visited set are all by position, so that the grid
+// fallback can dismiss fully visited runs of cells with a few word reads.
+// Tours are written as city indices in both.
+struct CitySpace {
+    __device__ __forceinline__ int32_t from_city(const GridView &, int32_t c) const { return c; }
+    __device__ __forceinline__ int32_t to_city(const GridView &, int32_t c) const { return c; }
+    template <class Vis, class Visited>
+    __device__ __forceinline__ int32_t fallback(const GridView &g, const int32_t *xy, int32_t c,
+                                                const Vis &, const Visited &visited) const
+    {
+        return fallback_city(g, xy, c, visited);
+    }
+};
+struct PositionSpace {
+    __device__ __forceinline__ int32_t from_city(const GridView &g, int32_t c) const
+    {
+        return g.pinv[c];
+    }
+    __device__ __forceinline__ int32_t to_city(const GridView &g, int32_t q) const
+    {
+        return g.pts[q].z;
+    }
+    template <class Visited>
+    __device__ __forceinline__ int32_t fallback(const GridView &g, const int32_t *, int32_t c,
+                                                const VisBits &vis, const Visited &) const
+    {
+        return fallback_position(g, c, VisitedByPosition{vis.w});
+    }
+};
+
 struct AntTask {
     const int32_t *xy;     // [n][2]
-    const CandW *rows;     // [n][k]
+    const CandW *rows;     // [n][k], rows and entries in the ant's city space
     int32_t n, k;
     uint32_t ant;          // absolute ant index (Philox counter word 1)
     uint32_t iteration;    // Philox counter word 2
@@ -99,22 +136,24 @@ struct AntTask {
 // so the inner loop holds only the step itself.
 // KP is the scan width, the smallest power of two >= k.  `grid()` returns the
 // instance's GridView (used by fallback steps).
-template <int KP, bool kProb, class Vis, class GridFn>
-__device__ void build_ant_impl(const AntTask &T, const Vis &vis, const GridFn &grid)
+template <int KP, bool kProb, class Space, class Vis, class GridFn>
+__device__ void build_ant_impl(const AntTask &T, const Vis &vis, const GridFn &grid,
+                               const Space &space)
 {
     const int lane = lane_id();
     const int32_t n = T.n, k = T.k;
     vis.clear(n, lane);
     auto visited = [&](int city) { return vis.test(city); };
 
+    const GridView g = grid();              // read once: no state carried through the loop
     uint32_t rnd = colony_draw(T.seed, T.iteration, T.ant, (uint32_t)lane);
     const uint32_t x0 = (uint32_t)read_lane_i32((int32_t)rnd, 0);
-    const int32_t start = (int32_t)(((uint64_t)x0 * (uint64_t)n) >> 32);
+    const int32_t start_city = (int32_t)(((uint64_t)x0 * (uint64_t)n) >> 32);
+    const int32_t start = space.from_city(g, start_city);
     if (lane == 0) vis.set(start);
 
     const bool active = lane < k;
     const int lr = active ? lane : k - 1;   // idle lanes re-read a valid element
-    const GridView g = grid();              // read once: no state carried through the loop
     int32_t c = start;
 
     CandW e = T.rows[(int64_t)c * k + lr];
@@ -158,7 +197,7 @@ __device__ void build_ant_impl(const AntTask &T, const Vis &vis, const GridFn &g
                 slot = (uint32_t)f;
                 if constexpr (kProb) prob = (float)(read_lane_f64(wv, f) / S);
             } else {
-                jn = fallback_city(g, T.xy, c, visited);
+                jn = space.fallback(g, T.xy, c, vis, visited);
                 slot = kNoSlot;
             }
             // a city index is always in range here; the clamp only keeps a logic
@@ -177,20 +216,21 @@ __device__ void build_ant_impl(const AntTask &T, const Vis &vis, const GridFn &g
             c = jn;
         }
         if (base + lane <= last) {
-            T.tour[base + lane] = st_city;
+            T.tour[base + lane] = space.to_city(g, st_city);
             T.slots[base + lane] = (uint8_t)st_slot;
             if constexpr (kProb) T.prob[base + lane] = st_prob;
         }
     }
 }
 
-template <int KP, class Vis, class GridFn>
-__device__ void build_ant(const AntTask &T, const Vis &vis, const GridFn &grid)
+template <int KP, class Space = CitySpace, class Vis, class GridFn>
+__device__ void build_ant(const AntTask &T, const Vis &vis, const GridFn &grid,
+                          const Space &space = Space())
 {
     if (T.prob)
-        build_ant_impl<KP, true>(T, vis, grid);
+        build_ant_impl<KP, true>(T, vis, grid, space);
     else
-        build_ant_impl<KP, false>(T, vis, grid);
+        build_ant_impl<KP, false>(T, vis, grid, space);
 }
 
 // The kx nearest cities of city `me` in (d, index) order, by one thread:

@@ -1,8 +1,9 @@
 // Tour construction with the random proportional rule (Section 2, Eq. 1), one
 // instance.
 //
-// One ant per 64-wide wavefront.  Per step the ant at city c reads the packed
-// candidate row {nn[c][r], w[c][r]} (one 128-byte line at k = 16), tests the
+// One ant per 64-wide wavefront, cities named by their position in the grid's
+// cell order.  Per step the ant at city c reads the packed candidate row
+// {nn[c][r], w[c][r]} (one 128-byte line at k = 16), tests the
 // candidates against its visited bitmask in LDS, forms the FP64 running sum of
 // the unvisited weights across lanes, and picks the first lane whose running
 // sum exceeds u * S with a ballot.  When no unvisited candidate has positive
@@ -14,15 +15,22 @@
 
 namespace aco {
 
-// Choice weights of every row (thread per city).
-__global__ void k_choice_info(const int32_t *__restrict__ nn, const float *__restrict__ tau,
+// Choice weights of every row (thread per position in cell order): row q is
+// the row of city pts[q], and its candidates are named by position.
+struct ToPosition {
+    const int32_t *pinv;
+    __device__ __forceinline__ int32_t operator()(int32_t c) const { return pinv[c]; }
+};
+
+__global__ void k_choice_info(const int4 *__restrict__ pts, const int32_t *__restrict__ pinv,
+                              const int32_t *__restrict__ nn, const float *__restrict__ tau,
                               const float *__restrict__ eta_b, int32_t n, int32_t k, double alpha,
                               CandW *__restrict__ rows)
 {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t rb = i * k;
-    choice_row(nn + rb, tau + rb, eta_b + rb, k, alpha, rows + rb);
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int64_t rb = (int64_t)pts[q].z * k;
+    choice_row(nn + rb, tau + rb, eta_b + rb, k, alpha, rows + q * k, ToPosition{pinv});
 }
 
 struct ConstructArgs {
@@ -56,7 +64,7 @@ __global__ __launch_bounds__(kWave) void k_construct(ConstructArgs A)
     T.tour = A.tours + (int64_t)a * A.n;
     T.slots = A.slots + (int64_t)a * A.n;
     T.prob = A.step_prob ? A.step_prob + (int64_t)a * A.n : nullptr;
-    build_ant<KP>(T, VisBits{vis}, [&]() { return grid_view(A.grid); });
+    build_ant<KP>(T, VisBits{vis}, [&]() { return grid_view(A.grid); }, PositionSpace());
     if (lane_id() == 0) A.lengths[a] = 0;       // summed by k_tour_length
 }
 
@@ -124,7 +132,11 @@ extern "C" int aco_construct_tours(const int32_t *xy, int32_t n, int32_t k, cons
                     max_lds_per_block());
     hipStream_t st = as_stream(stream);
     CandW *rows = (CandW *)ws;
-    k_choice_info<<<blocks_for(n, 256), 256, 0, st>>>(nn, tau, eta_b, n, k, alpha, rows);
+    const GridLayout lay(n);
+    const int4 *pts = (const int4 *)((const char *)grid + lay.pts);
+    const int32_t *pinv = (const int32_t *)((const char *)grid + lay.pinv);
+    k_choice_info<<<blocks_for(n, 256), 256, 0, st>>>(pts, pinv, nn, tau, eta_b, n, k, alpha,
+                                                        rows);
     ACO_LAUNCH_CHECK("k_choice_info");
     void (*kern)(ConstructArgs) = k <= 8    ? k_construct<8>
                                   : k <= 16 ? k_construct<16>

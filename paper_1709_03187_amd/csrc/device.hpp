@@ -151,18 +151,23 @@ struct GridHdr {
 constexpr int kExtWidth = 64;
 __host__ __device__ inline int ext_width(int64_t n) { return n - 1 < kExtWidth ? (int)(n - 1) : kExtWidth; }
 
+// A city's position is its index in `pts` (cell order).  The single-instance
+// construction works on positions, so that the cities of a run of cells in
+// one grid row are one contiguous range of a position-indexed visited set.
 struct GridView {
     GridHdr h;
     const int32_t *cell_start;   // [ncell + 1]
     const int4 *pts;             // [n] {x, y, city, 0} in cell order
     const int32_t *ext;          // [n][ext_stride], first kx entries of a row valid
     int32_t ext_stride;
+    const int32_t *pinv;         // [n] position of each city (nullptr where not built)
+    const int32_t *ext_pos;      // [n][ext_stride]: ext by position, entries positions
 };
 
 // Byte layout of the grid buffer (offsets aligned to 256 bytes).
 struct GridLayout {
     static constexpr size_t kAuxOffset = 128;   // 8-byte scratch slot inside the header block
-    size_t hdr, cell_start, cursor, pts, ext, total;
+    size_t hdr, cell_start, cursor, pts, ext, pinv, ext_pos, total;
     static __host__ __device__ size_t align(size_t v) { return (v + 255) & ~(size_t)255; }
     static __host__ __device__ int64_t cap_for(int64_t n) { return 3 * n + 2; }
     __host__ __device__ explicit GridLayout(int64_t n)
@@ -173,7 +178,9 @@ struct GridLayout {
         cursor = align(cell_start + (size_t)(cap + 1) * 4);
         pts = align(cursor + (size_t)cap * 4);
         ext = align(pts + (size_t)n * 16);
-        total = align(ext + (size_t)n * ext_width(n) * 4);
+        pinv = align(ext + (size_t)n * ext_width(n) * 4);
+        ext_pos = align(pinv + (size_t)n * 4);
+        total = align(ext_pos + (size_t)n * ext_width(n) * 4);
     }
 };
 
@@ -187,6 +194,8 @@ __device__ __forceinline__ GridView grid_view(const void *grid)
     g.pts = (const int4 *)(b + L.pts);
     g.ext = (const int32_t *)(b + L.ext);
     g.ext_stride = g.h.kx;
+    g.pinv = (const int32_t *)(b + L.pinv);
+    g.ext_pos = (const int32_t *)(b + L.ext_pos);
     return g;
 }
 
@@ -318,19 +327,49 @@ __device__ __forceinline__ int closer_block_radius(const GridHdr &h, int64_t d_l
     return (int)((t < lim ? t : lim) - 1);
 }
 
+// How the grid search sees the visited set.  By city: each point is tested
+// by its city index.  By position: the set is indexed by position in `pts`,
+// a point is tested by its position and a whole range of positions (the
+// cities of a run of cells) can be found visited with a few word reads.
+template <class Visited>
+struct VisitedByCity {
+    const Visited &visited;
+    __device__ __forceinline__ bool test(int64_t, int32_t city) const { return visited(city); }
+    __device__ __forceinline__ bool all_visited(int32_t, int32_t) const { return false; }
+};
+struct VisitedByPosition {
+    const uint32_t *w;   // bit q: position q visited
+    __device__ __forceinline__ bool test(int64_t q, int32_t) const
+    {
+        return (w[q >> 5] >> (q & 31)) & 1u;
+    }
+    // true when every position in [a, b) is visited (or the range is empty)
+    __device__ __forceinline__ bool all_visited(int32_t a, int32_t b) const
+    {
+        for (int32_t q = a; q < b; q = (q | 31) + 1) {
+            const uint32_t lo = q & 31;
+            const uint32_t hi = (b - (q & ~31)) >= 32 ? 32u : (uint32_t)(b - (q & ~31));
+            const uint32_t mask = (hi == 32u ? ~0u : ((1u << hi) - 1u)) & ~((1u << lo) - 1u);
+            if (~w[q >> 5] & mask) return false;
+        }
+        return true;
+    }
+};
+
 // Nearest unvisited city to (cx, cy) by key (d, city), searched by the whole
 // wave over square blocks of cells: radius 1 first (or, given that no
 // unvisited city is closer than d_lo, the first ring outside the block that
-// holds only closer cities), then one more ring per pass.  Each pass reads the
-// new cells as contiguous row ranges of `pts`, one city per lane, and keeps a
-// lane-local minimum (the distance is only rounded for cities that can beat
-// it); one wave reduction per pass.  The search stops once every city outside
-// the searched block is provably farther than the best distance found
-// (bound > d_best), so the result is exact.
-// Returns (d << 32) | city, or ~0 if every city is visited.
-template <class Visited>
+// holds only closer cities), then one more ring per pass.  Each pass reads
+// the new cells as contiguous row ranges of `pts`; ranges the visited set
+// shows fully visited are dropped before any point is read; the rest are
+// read one city per lane, keeping a lane-local minimum (the distance is only
+// rounded for cities that can beat it); one wave reduction per pass.  The
+// search stops once every city outside the searched block is provably
+// farther than the best distance found (bound > d_best), so the result is
+// exact.  Returns (d << 32) | city, or ~0 if every city is visited.
+template <class Vis>
 __device__ uint64_t wave_nearest_unvisited(const GridView &g, int32_t cx, int32_t cy,
-                                           const Visited &visited, int64_t d_lo = 0)
+                                           const Vis &vis, int64_t d_lo = 0)
 {
     const GridHdr &h = g.h;
     const int lane = lane_id();
@@ -346,6 +385,7 @@ __device__ uint64_t wave_nearest_unvisited(const GridView &g, int32_t cx, int32_
             if (s < nslots && block_slot(h, gx, gy, rin, r, s, row, xa, xb)) {
                 a = g.cell_start[(int64_t)row * h.gw + xa];
                 b = g.cell_start[(int64_t)row * h.gw + xb + 1];
+                if (vis.all_visited(a, b)) b = a;
             }
             const int len = b - a;
             const int incl = wave_incl_scan_i32_dpp(len);
@@ -365,9 +405,10 @@ __device__ uint64_t wave_nearest_unvisited(const GridView &g, int32_t cx, int32_
                 const int pa = __shfl(a, lo);
                 const int pe = __shfl(excl, lo);
                 if (idx < total) {
-                    const int4 pt = g.pts[pa + (idx - pe)];
+                    const int64_t q = pa + (idx - pe);
+                    const int4 pt = g.pts[q];
                     const int64_t s2 = sq_dist(cx, cy, pt.x, pt.y);
-                    if (s2 <= s_cut && !visited(pt.z)) {
+                    if (s2 <= s_cut && !vis.test(q, pt.z)) {
                         const uint32_t d = (uint32_t)nint_sqrt(s2);
                         const uint64_t key = ((uint64_t)d << 32) | (uint32_t)pt.z;
                         if (key < best) {
@@ -414,7 +455,32 @@ __device__ int32_t fallback_city(const GridView &g, const int32_t *xy, int32_t c
     const int32_t cx = xy[2 * (int64_t)c], cy = xy[2 * (int64_t)c + 1];
     const int32_t jl = read_lane_i32(j, kx - 1);
     const int64_t d_lo = nint_sqrt(sq_dist(cx, cy, xy[2 * (int64_t)jl], xy[2 * (int64_t)jl + 1]));
-    return (int32_t)(uint32_t)wave_nearest_unvisited(g, cx, cy, visited, d_lo);
+    return (int32_t)(uint32_t)wave_nearest_unvisited(g, cx, cy, VisitedByCity<Visited>{visited}, d_lo);
+}
+
+// The same fallback on positions: c and the result are positions in `pts`,
+// `vis` is the position-indexed visited set.  Ties still go to the lower
+// city index (keys carry the city).
+__device__ __forceinline__ int32_t fallback_position(const GridView &g, int32_t c,
+                                                     const VisitedByPosition &vis)
+{
+    const int lane = lane_id();
+    const int kx = g.h.kx;
+    bool unv = false;
+    int32_t j = 0;
+    if (lane < kx) {
+        j = g.ext_pos[(int64_t)c * g.ext_stride + lane];
+        unv = !vis.test(j, 0);
+    }
+    const uint64_t bal = __ballot(unv);
+    if (bal) return read_lane_i32(j, __ffsll((unsigned long long)bal) - 1);
+    const int4 me = g.pts[c];
+    const int32_t jl = read_lane_i32(j, kx - 1);
+    const int4 pl = g.pts[jl];
+    const int64_t d_lo = nint_sqrt(sq_dist(me.x, me.y, pl.x, pl.y));
+    const uint64_t best = wave_nearest_unvisited(g, me.x, me.y, vis, d_lo);
+    if (best == ~0ull) return -1;
+    return g.pinv[(uint32_t)best];
 }
 
 }  // namespace aco
