@@ -183,8 +183,9 @@ __global__ void k_eta(const int32_t *__restrict__ nnd, const float *__restrict__
 
 // ------------------------------------------------------------------ NN tour
 
-// The nearest-neighbour tour from city 0 by one wave (the visited bits are the
-// workgroup's LDS).
+// The nearest-neighbour tour from city 0 by one wave on cell-order positions
+// (the visited bits are the workgroup's LDS).  nn and nnd are not needed: the
+// grid's 64-NN table by position starts with the candidate list.
 __global__ __launch_bounds__(kWave) void k_nn_tour(const int32_t *__restrict__ xy, int32_t n,
                                                    int32_t k, const int32_t *__restrict__ nn,
                                                    const int32_t *__restrict__ nnd,
@@ -192,7 +193,7 @@ __global__ __launch_bounds__(kWave) void k_nn_tour(const int32_t *__restrict__ x
                                                    int64_t *length)
 {
     extern __shared__ uint32_t vis[];
-    const int64_t L = nn_tour_wave(xy, n, k, nn, nnd, grid_view(grid), VisBits{vis}, tour);
+    const int64_t L = nn_tour_positions(grid_view(grid), n, VisBits{vis}, tour);
     if (lane_id() == 0) *length = L;
 }
 

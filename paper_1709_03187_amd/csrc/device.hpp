@@ -359,7 +359,8 @@ struct VisitedByPosition {
 // Nearest unvisited city to (cx, cy) by key (d, city), searched by the whole
 // wave over square blocks of cells: radius 1 first (or, given that no
 // unvisited city is closer than d_lo, the first ring outside the block that
-// holds only closer cities), then one more ring per pass.  Each pass reads
+// holds only closer cities), then rings outward: one per pass, doubling (up to
+// 16) after every pass that finds no unvisited city.  Each pass reads
 // the new cells as contiguous row ranges of `pts`; ranges the visited set
 // shows fully visited are dropped before any point is read; the rest are
 // read one city per lane, keeping a lane-local minimum (the distance is only
@@ -377,7 +378,8 @@ __device__ uint64_t wave_nearest_unvisited(const GridView &g, int32_t cx, int32_
     uint64_t best = ~0ull;
     int64_t s_cut = INT64_MAX;   // cities with s > s_cut cannot beat this lane's best
     int rin = closer_block_radius(h, d_lo);
-    for (int r = rin < 0 ? 1 : rin + 1;; rin = r, r = r + 1) {
+    int width = 1;   // rings per pass: doubles after every pass that finds nothing
+    for (int r = rin < 0 ? 1 : rin + 1;; rin = r, r = r + width) {
         const int nslots = 2 * (2 * r + 1);
         for (int sb = 0; sb < nslots; sb += kWave) {
             const int s = sb + lane;
@@ -423,6 +425,9 @@ __device__ uint64_t wave_nearest_unvisited(const GridView &g, int32_t cx, int32_
         if (best != ~0ull) {
             const int64_t d = (int64_t)(best >> 32);
             s_cut = d * d + d;
+            width = 1;
+        } else if (width < 16) {
+            width *= 2;
         }
         int64_t bound;
         if (!outside_bound(h, cx, cy, gx, gy, r, bound)) break;
