@@ -186,15 +186,32 @@ __global__ void k_eta(const int32_t *__restrict__ nnd, const float *__restrict__
 // The nearest-neighbour tour from city 0 by one wave on cell-order positions
 // (the visited bits are the workgroup's LDS).  nn and nnd are not needed: the
 // grid's 64-NN table by position starts with the candidate list.
-__global__ __launch_bounds__(kWave) void k_nn_tour(const int32_t *__restrict__ xy, int32_t n,
-                                                   int32_t k, const int32_t *__restrict__ nn,
-                                                   const int32_t *__restrict__ nnd,
-                                                   const void *grid, int32_t *tour,
-                                                   int64_t *length)
+__global__ __launch_bounds__(kWave) void k_nn_tour(int32_t n, const void *grid, int32_t *tour)
 {
     extern __shared__ uint32_t vis[];
-    const int64_t L = nn_tour_positions(grid_view(grid), n, VisBits{vis}, tour);
-    if (lane_id() == 0) *length = L;
+    nn_tour_positions(grid_view(grid), n, VisBits{vis}, tour);
+}
+
+// Closed length of one tour by one workgroup of 256 threads (exact integer
+// sum; the order of the additions does not matter).
+__global__ __launch_bounds__(256) void k_closed_length(const int32_t *__restrict__ xy,
+                                                       const int32_t *__restrict__ tour,
+                                                       int32_t n, int64_t *length)
+{
+    __shared__ int64_t part[256 / kWave];
+    int64_t s = 0;
+    for (int32_t t = threadIdx.x; t < n; t += blockDim.x) {
+        const int64_t a = tour[t], b = tour[t + 1 < n ? t + 1 : 0];
+        s += nint_sqrt(sq_dist(xy[2 * a], xy[2 * a + 1], xy[2 * b], xy[2 * b + 1]));
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int w = 0; w < (int)(blockDim.x / kWave); ++w) t += part[w];
+        *length = t;
+    }
 }
 
 __global__ void k_fill_f32(float *p, int64_t count, float v)
@@ -314,8 +331,10 @@ extern "C" int aco_init_pheromone(const int32_t *xy, int32_t n, int32_t k, const
     if (lds > 65536)
         ACO_HIP_CHECK(hipFuncSetAttribute((const void *)k_nn_tour,
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    k_nn_tour<<<1, kWave, lds, st>>>(xy, n, k, nn, nnd, grid, nn_tour, dlen);
+    k_nn_tour<<<1, kWave, lds, st>>>(n, grid, nn_tour);
     ACO_LAUNCH_CHECK("k_nn_tour");
+    k_closed_length<<<1, 256, 0, st>>>(xy, nn_tour, n, dlen);
+    ACO_LAUNCH_CHECK("k_closed_length");
     int64_t L = 0;
     ACO_HIP_CHECK(hipMemcpyAsync(&L, dlen, 8, hipMemcpyDeviceToHost, st));
     ACO_HIP_CHECK(hipStreamSynchronize(st));

@@ -324,48 +324,39 @@ __device__ int64_t nn_tour_wave(const int32_t *__restrict__ xy, int32_t n, int32
 
 // The nearest-neighbour tour from city 0 by one wave, on positions: the
 // nearest unvisited city is the first unvisited entry of the current city's
-// 64-NN row (the candidate list is its prefix, in the same order), else the
-// grid's nearest unvisited city.  Writes the tour as city indices and returns
-// its closed length.
-__device__ inline int64_t nn_tour_positions(const GridView &g, int32_t n, const VisBits &vis,
-                                            int32_t *tour)
+// 64-NN row (the candidate list is its prefix, in the same order; the first
+// 16 entries, one line, settle most steps), else the grid's nearest
+// unvisited city.  Writes the tour as city indices; its length is summed
+// afterwards, off this sequential loop.
+__device__ inline void nn_tour_positions(const GridView &g, int32_t n, const VisBits &vis,
+                                         int32_t *tour)
 {
     const int lane = lane_id();
     vis.clear(n, lane);
-    const int kx = g.h.kx;
+    const int kFirst = g.h.kx < 16 ? g.h.kx : 16;
     const VisitedByPosition vp{vis.w};
     int32_t c = g.pinv[0];
     if (lane == 0) vis.set(c);
-    int4 pc = g.pts[c];
-    const int4 p0 = pc;
-    int4 pn = pc;        // the city chosen last step; its edge is added one step later,
-    int64_t L = 0;       // so that its coordinate load overlaps the next row load
-    int32_t stage = 0;   // lane t holds tour[base + t] (city indices)
+    int32_t stage = c;   // lane t holds the position of tour[base + t]
     for (int32_t t = 1; t < n; ++t) {
         int32_t j = 0;
         bool unv = false;
-        if (lane < kx) {
+        if (lane < kFirst) {
             j = g.ext_pos[(int64_t)c * g.ext_stride + lane];
             unv = !vis.test(j);
         }
-        L += nint_sqrt(sq_dist(pc.x, pc.y, pn.x, pn.y));
-        pc = pn;
         const uint64_t bal = __ballot(unv);
         int32_t jn = bal ? read_lane_i32(j, __ffsll((unsigned long long)bal) - 1)
                          : fallback_position(g, c, vp);
         jn = ((uint32_t)jn < (uint32_t)n) ? jn : c;   // range guard, as in build_ant
-        pn = g.pts[jn];
         if (lane == 0) vis.set(jn);
-        if (lane == (t & 63)) stage = pn.z;
+        if (lane == (t & 63)) stage = jn;
         if ((t & 63) == 63 || t == n - 1) {
             const int32_t base = t & ~63;
-            if (base + lane <= t) tour[base + lane] = stage;
+            if (base + lane <= t) tour[base + lane] = g.pts[stage].z;
         }
         c = jn;
     }
-    L += nint_sqrt(sq_dist(pc.x, pc.y, pn.x, pn.y));
-    L += nint_sqrt(sq_dist(pn.x, pn.y, p0.x, p0.y));
-    return L;
 }
 
 }  // namespace aco
