@@ -35,19 +35,19 @@ __device__ __forceinline__ int find_slot(const int32_t *__restrict__ nn, int64_t
     return -1;
 }
 
-// One thread per tour edge (tour[t], tour[t+1 mod n]) of every ant.  The slot
-// of the forward direction comes from the construction record when it names
-// the edge; the reverse slot from rev[] or, for edges outside the forward
-// list, a scan of the other row.
+// One thread per tour edge (tour[t], tour[t+1 mod n]): ant a = blockIdx.y
+// (a 2-D grid, so no index division).  The slot of the forward direction
+// comes from the construction record when it names the edge; the reverse
+// slot from rev[] or, for edges outside the forward list, a scan of the other
+// row.
 __global__ void k_deposit(const int32_t *__restrict__ nn, const int8_t *__restrict__ rev,
-                          int32_t n, int32_t k, int32_t m, const int32_t *__restrict__ tours,
+                          int32_t n, int32_t k, int32_t a0, const int32_t *__restrict__ tours,
                           const uint8_t *__restrict__ slots, const int64_t *__restrict__ q,
                           unsigned long long *__restrict__ acc)
 {
-    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (e >= (int64_t)m * n) return;
-    const int32_t a = (int32_t)(e / n);
-    const int32_t t = (int32_t)(e - (int64_t)a * n);
+    const int32_t a = a0 + (int32_t)blockIdx.y;
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
     const int64_t base = (int64_t)a * n;
     const int32_t i = tours[base + t];
     const int32_t j = tours[base + (t + 1 == n ? 0 : t + 1)];
@@ -186,8 +186,11 @@ extern "C" int aco_update_pheromone(int32_t n, int32_t k, const int32_t *nn, con
     int64_t *q = (int64_t *)((char *)ws + (size_t)nk * 8);
     k_zero_i64<<<std::min(4096u, blocks_for(nk, 256)), 256, 0, st>>>(acc, nk);
     k_quanta<<<blocks_for(m, 256), 256, 0, st>>>(lengths, m, deposit_shift, q);
-    k_deposit<<<blocks_for((int64_t)m * n, 256), 256, 0, st>>>(
-        nn, rev, n, k, m, tours, slots, q, (unsigned long long *)acc);
+    for (int32_t a0 = 0; a0 < m; a0 += 65535) {   // grid y is at most 65,535 ants
+        const int32_t ma = m - a0 < 65535 ? m - a0 : 65535;
+        k_deposit<<<dim3(blocks_for(n, 256), (unsigned)ma), 256, 0, st>>>(
+            nn, rev, n, k, a0, tours, slots, q, (unsigned long long *)acc);
+    }
     const float f = (float)(1.0 - rho);
     const float scale = std::ldexp(1.0f, -deposit_shift);
     k_merge<<<std::min(8192u, blocks_for(nk, 256)), 256, 0, st>>>(tau, acc, nn, rev, k, nk, f,
