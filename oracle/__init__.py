@@ -39,6 +39,8 @@ PINS = {
     "construct/replay": "exact rational probabilities (fractions); exhaustive tour enumeration (n<=7); "
                         "uniform permutations for alpha=beta=0, k=n-1; invariants",
     "update": "pure-evaporation closed form; numpy float32 merge; integer conservation; symmetry",
+    "partial (PartialACO)": "p=0 equals the full construction; r=1 gives the rotated local best; "
+                            "exact rational completion probabilities (n=7); plan statistics",
 }
 
 
@@ -82,6 +84,11 @@ def lib():
             "oracle_update": (None, [i64, C.c_int, p, p, i64, p, p, dbl, C.c_int]),
             "oracle_run": (C.c_int, [i64, C.c_int, p, i64, dbl, dbl, dbl, i64, u64, C.c_int,
                                      C.c_int, p, p, p, p]),
+            "oracle_partial_plan": (None, [u64, i64, i64, i64, u64, i64, p, p, p]),
+            "oracle_construct_partial": (None, [i64, C.c_int, p, p, p, p, p, dbl, dbl, u64, i64,
+                                                p, i64, p, u64, i64, p, p, p, p]),
+            "oracle_replay_partial": (None, [i64, C.c_int, p, p, p, p, p, dbl, dbl, u64, i64, i64,
+                                             p, u64, i64, p, dbl, p, p]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(L, name)
@@ -242,6 +249,77 @@ def replay(xy, nn, nnd, tau, alpha, beta, seed, iteration, ant, tour, eta=None,
                         float(beta), int(seed), int(iteration), int(ant), _p(tour),
                         float(boundary_eps), _p(prob), _p(out))
     return {f: int(out[i]) for i, f in enumerate(REPLAY_FIELDS)}, prob
+
+
+# ---------------------------------------------------------------- PartialACO
+def p_threshold(p: float) -> int:
+    """Threshold P = round(p 2^32) of the partial-modification draw (x1 < P)."""
+    return int(min(max(round(float(p) * 2.0**32), 0), 2**32))
+
+
+def partial_plan(seed, iteration, ant, n, p, max_modify):
+    """(start position, partial?, cities rebuilt) of one ant (Section 3.1, Algorithm 1)."""
+    s, r = C.c_int64(0), C.c_int64(0)
+    part = C.c_int(0)
+    lib().oracle_partial_plan(int(seed), int(iteration), int(ant), int(n), p_threshold(p),
+                              int(max_modify), C.byref(s), C.byref(part), C.byref(r))
+    return int(s.value), bool(part.value), int(r.value)
+
+
+def construct_partial(xy, nn, nnd, tau, alpha, beta, seed, iteration, ants, lbest, p, max_modify,
+                      eta=None):
+    """PartialACO construction of the listed ants; lbest [len(ants)][n] are their local bests.
+    Returns dict(tours, lengths, slots, probs)."""
+    xy = _xy(xy)
+    n = len(xy)
+    nn = np.ascontiguousarray(nn, np.int32)
+    nnd = np.ascontiguousarray(nnd, np.int32)
+    tau = np.ascontiguousarray(tau, np.float32)
+    eta = None if eta is None else np.ascontiguousarray(eta, np.float64)
+    ants = np.ascontiguousarray(ants, np.int64)
+    lbest = np.ascontiguousarray(lbest, np.int32)
+    A = len(ants)
+    tours = np.empty((A, n), np.int32)
+    lengths = np.empty(A, np.int64)
+    slots = np.empty((A, n), np.int8)
+    probs = np.empty((A, n), np.float64)
+    lib().oracle_construct_partial(n, nn.shape[1], _p(xy), _p(nn), _p(nnd), _p(tau), _p(eta),
+                                   float(alpha), float(beta), int(seed), int(iteration), _p(ants),
+                                   A, _p(lbest), p_threshold(p), int(max_modify), _p(tours),
+                                   _p(lengths), _p(slots), _p(probs))
+    return dict(tours=tours, lengths=lengths, slots=slots, probs=probs)
+
+
+def replay_partial(xy, nn, nnd, tau, alpha, beta, seed, iteration, ant, lbest, p, max_modify,
+                   tour, eta=None, boundary_eps=1e-6):
+    """Teacher-forced replay of a PartialACO tour.  Returns (counts dict with 'kept', prob)."""
+    xy = _xy(xy)
+    n = len(xy)
+    nn = np.ascontiguousarray(nn, np.int32)
+    nnd = np.ascontiguousarray(nnd, np.int32)
+    tau = np.ascontiguousarray(tau, np.float32)
+    eta = None if eta is None else np.ascontiguousarray(eta, np.float64)
+    lbest = np.ascontiguousarray(lbest, np.int32)
+    tour = np.ascontiguousarray(tour, np.int32)
+    prob = np.zeros(n, np.float64)
+    out = np.zeros(8, np.int64)
+    lib().oracle_replay_partial(n, nn.shape[1], _p(xy), _p(nn), _p(nnd), _p(tau), _p(eta),
+                                float(alpha), float(beta), int(seed), int(iteration), int(ant),
+                                _p(lbest), p_threshold(p), int(max_modify), _p(tour),
+                                float(boundary_eps), _p(prob), _p(out))
+    res = {f: int(out[i]) for i, f in enumerate(REPLAY_FIELDS)}
+    res["kept"] = int(out[7])
+    return res, prob
+
+
+def update_local_best(lbest, lbest_len, tours, lengths):
+    """Algorithm 1: an ant's local best is replaced only by a strictly shorter tour."""
+    lbest = np.array(lbest, np.int32, copy=True)
+    lbest_len = np.array(lbest_len, np.int64, copy=True)
+    better = np.asarray(lengths) < lbest_len
+    lbest[better] = np.asarray(tours)[better]
+    lbest_len[better] = np.asarray(lengths)[better]
+    return lbest, lbest_len
 
 
 # ---------------------------------------------------------------- update

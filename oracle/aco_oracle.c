@@ -398,20 +398,23 @@ static ant_result_t construct_ant(const colony_t *C, int64_t ant, int32_t *tour,
  *   6 steps where u is within boundary_eps of a cumulative boundary (any outcome).
  * prob[t] receives the oracle's probability of the move the tour takes
  * (-1 for a fallback step, 0 if the move has zero probability). */
-void oracle_replay_ant(const colony_t *C, int64_t ant, const int32_t *tour, double boundary_eps,
-                       double *prob, int64_t *out)
+/* Replay of steps first..n-1 of `tour` after its first `first` cities have
+ * been marked visited (they are checked by the caller). */
+static void replay_from(const colony_t *C, int64_t ant, const int32_t *tour, int64_t first,
+                        double boundary_eps, double *prob, int64_t *out)
 {
     int64_t n = C->n;
     int k = C->k;
     uint8_t *vis = (uint8_t *)calloc((size_t)n, 1);
     double w[64], cum[64];
-    memset(out, 0, 8 * sizeof(int64_t));
-    int64_t c = tour[0];
-    if (c != oracle_start_city(C->seed, C->iteration, ant, n)) out[5]++;
-    if (c < 0 || c >= n) { out[5]++; free(vis); return; }
-    vis[c] = 1;
-    prob[0] = 1.0;
-    for (int64_t t = 1; t < n; t++) {
+    int64_t c = -1;
+    for (int64_t t = 0; t < first; t++) {
+        c = tour[t];
+        if (c < 0 || c >= n || vis[c]) { out[5]++; free(vis); return; }
+        vis[c] = 1;
+        prob[t] = 1.0;
+    }
+    for (int64_t t = first; t < n; t++) {
         int64_t j = tour[t];
         out[0]++;
         if (j < 0 || j >= n || vis[j]) { out[5]++; prob[t] = 0.0; break; }
@@ -442,6 +445,141 @@ void oracle_replay_ant(const colony_t *C, int64_t ant, const int32_t *tour, doub
         c = j;
     }
     free(vis);
+}
+
+void oracle_replay_ant(const colony_t *C, int64_t ant, const int32_t *tour, double boundary_eps,
+                       double *prob, int64_t *out)
+{
+    memset(out, 0, 8 * sizeof(int64_t));
+    if (tour[0] != oracle_start_city(C->seed, C->iteration, ant, C->n)) out[5]++;
+    replay_from(C, ant, tour, 1, boundary_eps, prob, out);
+}
+
+/* ------------------------------------------------------------------ */
+/* PartialACO (Section 3.1, Algorithm 1): each ant keeps a random part   */
+/* of its local best tour and rebuilds the rest.  The plan of ant a at   */
+/* an iteration comes from the Philox block at counter (0, a, iteration):*/
+/*   word 0: start position s = (x0 n) >> 32 in the local best tour (for */
+/*           a full construction this is the usual start city);          */
+/*   word 1: the ant only partially modifies its tour when x1 < P, with  */
+/*           P = round(p 2^32) for the probability p (Section 4);        */
+/*   word 2: it rebuilds r = 1 + ((x2 M) >> 32) cities, uniform in       */
+/*           [1, M], M the cap on the modified share (Section 4).         */
+/* The kept part is lbest[s], ..., lbest[s + n - r - 1] (cyclic); the   */
+/* rest is constructed with Eq. 1 from the last kept city, the step at  */
+/* tour position t drawing from counter (t, a, iteration) as always.     */
+/* ------------------------------------------------------------------ */
+
+void oracle_partial_plan(uint64_t seed, int64_t iteration, int64_t ant, int64_t n,
+                         uint64_t p_threshold, int64_t max_modify, int64_t *start,
+                         int *partial, int64_t *rebuild)
+{
+    uint32_t ctr[4] = {0u, (uint32_t)ant, (uint32_t)iteration, 0u};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t w[4];
+    oracle_philox4x32_10(ctr, key, w);
+    int64_t M = max_modify < 1 ? 1 : (max_modify > n - 1 ? n - 1 : max_modify);
+    *start = (int64_t)(((uint64_t)w[0] * (uint64_t)n) >> 32);
+    *partial = (uint64_t)w[1] < p_threshold;
+    *rebuild = 1 + (int64_t)(((uint64_t)w[2] * (uint64_t)M) >> 32);
+}
+
+static ant_result_t construct_partial_ant(const colony_t *C, int64_t ant, const int32_t *lbest,
+                                          uint64_t p_threshold, int64_t max_modify,
+                                          int32_t *tour, int8_t *slot, double *prob)
+{
+    int64_t n = C->n, s, r;
+    int partial;
+    oracle_partial_plan(C->seed, C->iteration, ant, n, p_threshold, max_modify, &s, &partial, &r);
+    if (!partial) return construct_ant(C, ant, tour, slot, prob);
+    int k = C->k;
+    int64_t keep = n - r;
+    uint8_t *vis = (uint8_t *)calloc((size_t)n, 1);
+    double w[64], cum[64];
+    ant_result_t res = {0, 0};
+    int64_t c = -1;
+    for (int64_t t = 0; t < keep; t++) {
+        c = lbest[(s + t) % n];
+        vis[c] = 1;
+        tour[t] = (int32_t)c;
+        if (slot) slot[t] = -1;
+        if (prob) prob[t] = 1.0;
+        if (t > 0) res.length += oracle_dist(C->xy, tour[t - 1], c);
+    }
+    for (int64_t t = keep; t < n; t++) {
+        double u = (double)oracle_draw(C->seed, C->iteration, ant, t) * 0x1p-32;
+        int nu;
+        double S = row_weights(C, c, vis, w, cum, &nu);
+        int64_t j, d;
+        if (nu > 0 && S > 0.0) {
+            int q = roulette(C, w, cum, S, u);
+            j = C->nn[c * k + q];
+            d = C->nnd[c * k + q];
+            if (slot) slot[t] = (int8_t)q;
+            if (prob) prob[t] = w[q] / S;
+        } else {
+            j = nearest_unvisited(C->xy, n, c, vis, &d);
+            res.fallbacks++;
+            if (slot) slot[t] = -1;
+            if (prob) prob[t] = -1.0;
+        }
+        vis[j] = 1;
+        tour[t] = (int32_t)j;
+        res.length += d;
+        c = j;
+    }
+    res.length += oracle_dist(C->xy, c, tour[0]);
+    free(vis);
+    return res;
+}
+
+void oracle_construct_partial(int64_t n, int k, const int32_t *xy, const int32_t *nn,
+                              const int32_t *nnd, const float *tau, const double *eta,
+                              double alpha, double beta, uint64_t seed, int64_t iteration,
+                              const int64_t *ants, int64_t count, const int32_t *lbest,
+                              uint64_t p_threshold, int64_t max_modify, int32_t *tours,
+                              int64_t *lengths, int8_t *slots, double *probs)
+{
+    colony_t C;
+    C.n = n; C.k = k; C.xy = xy; C.nn = nn; C.nnd = nnd; C.tau = tau; C.eta = eta;
+    C.alpha = alpha; C.beta = beta; C.seed = seed; C.iteration = iteration;
+    for (int64_t q = 0; q < count; q++) {
+        ant_result_t r = construct_partial_ant(&C, ants[q], lbest + q * n, p_threshold,
+                                               max_modify, tours + q * n,
+                                               slots ? slots + q * n : NULL,
+                                               probs ? probs + q * n : NULL);
+        lengths[q] = r.length;
+    }
+}
+
+/* Teacher-forced replay of a PartialACO tour: the kept part must be the
+ * planned segment of lbest (each wrong city counts as invalid, out[5]);
+ * the rebuilt steps are replayed as in oracle_replay_ant.  out[7] receives
+ * the number of kept cities (n for none when the ant built a full tour:
+ * then the whole tour is replayed from its start city). */
+void oracle_replay_partial(int64_t n, int k, const int32_t *xy, const int32_t *nn,
+                           const int32_t *nnd, const float *tau, const double *eta, double alpha,
+                           double beta, uint64_t seed, int64_t iteration, int64_t ant,
+                           const int32_t *lbest, uint64_t p_threshold, int64_t max_modify,
+                           const int32_t *tour, double boundary_eps, double *prob, int64_t *out)
+{
+    colony_t C;
+    C.n = n; C.k = k; C.xy = xy; C.nn = nn; C.nnd = nnd; C.tau = tau; C.eta = eta;
+    C.alpha = alpha; C.beta = beta; C.seed = seed; C.iteration = iteration;
+    int64_t s, r;
+    int partial;
+    oracle_partial_plan(seed, iteration, ant, n, p_threshold, max_modify, &s, &partial, &r);
+    if (!partial) {
+        oracle_replay_ant(&C, ant, tour, boundary_eps, prob, out);
+        out[7] = n;
+        return;
+    }
+    memset(out, 0, 8 * sizeof(int64_t));
+    int64_t keep = n - r;
+    for (int64_t t = 0; t < keep; t++)
+        if (tour[t] != lbest[(s + t) % n]) out[5]++;
+    replay_from(&C, ant, tour, keep, boundary_eps, prob, out);
+    out[7] = keep;
 }
 
 /* ------------------------------------------------------------------ */
