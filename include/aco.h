@@ -246,6 +246,45 @@ int aco_run_batched(const int32_t *xy, const int64_t *offsets, int32_t B, const 
                     int32_t *tuned_out);
 
 /* ------------------------------------------------------------------------
+ * PartialACO (Section 3.1, Algorithm 1).  Each ant keeps part of its own
+ * best tour so far (its local best) and rebuilds only the rest with the rule
+ * of Eq. 1; Section 4 caps the rebuilt share and lets an ant build a full
+ * tour with probability 1 - p.  The plan of ant a at an iteration comes from
+ * the Philox block at counter (0, a, iteration): word 0 gives the start
+ * position s = (x0 n) >> 32 in the local best tour, word 1 the partial
+ * decision x1 < round(p 2^32), word 2 the rebuilt count
+ * r = 1 + ((x2 M) >> 32), uniform on [1, M] with M = max_modify clamped to
+ * [1, n-1].  A partial tour is lbest[s], ..., lbest[s + n - r - 1] (cyclic)
+ * followed by r cities constructed from the last kept city; tour position t
+ * draws from counter (t, a, iteration) as in aco_construct_tours, so an ant
+ * that builds a full tour (and p = 0) gives exactly aco_construct_tours'
+ * tour.  Kept positions carry slot 255 (no construction record) and step_prob 1.
+ * Iteration 0 is a full construction; the local bests start as its tours.
+ * ------------------------------------------------------------------------ */
+
+/* As aco_construct_tours, plus:
+ *   p_partial   probability in [0, 1] that an ant only partially rebuilds
+ *   max_modify  cap M >= 1 on the rebuilt cities (the paper uses 1% at 200K)
+ *   lbest       int32 [m][n] the ants' local best tours (city indices; row a
+ *               for ant ant0 + a), read only
+ * Errors: as aco_construct_tours; INVALID_ARG for lbest NULL, p outside
+ * [0, 1], max_modify < 1.  lbest rows must be permutations of 0..n-1. */
+int aco_construct_partial(const int32_t *xy, int32_t n, int32_t k, const int32_t *nn,
+                          const int32_t *nnd, const float *eta_b, const void *grid,
+                          const float *tau, int32_t m, int32_t ant0, double alpha, uint64_t seed,
+                          int64_t iteration, double p_partial, int32_t max_modify,
+                          const int32_t *lbest, int32_t *tours, int64_t *lengths, uint8_t *slots,
+                          float *step_prob, void *ws, size_t ws_bytes, void *stream);
+
+/* Local bests (Algorithm 1): for every ant a with lengths[a] < lbest_len[a],
+ * lbest[a] = tours[a] and lbest_len[a] = lengths[a] (strict improvement).
+ * Initialise lbest_len to INT64_MAX to take the first tours.
+ *   tours int32 [m][n], lengths int64 [m]; lbest int32 [m][n], lbest_len int64 [m]
+ * Errors: INVALID_ARG. */
+int aco_update_local_best(int32_t n, int32_t m, const int32_t *tours, const int64_t *lengths,
+                          int32_t *lbest, int64_t *lbest_len, void *stream);
+
+/* ------------------------------------------------------------------------
  * Learned heuristic.  A small network scores every candidate edge from its
  * local geometry, and sigmoid(score) replaces eta = 1/d in the weights
  * tau^alpha * eta^beta of Eq. 1 (Section 2); the colony itself is unchanged.

@@ -37,7 +37,8 @@ EXPORTS = (
     "aco_run_workspace_bytes", "aco_run", "aco_batch_workspace_bytes", "aco_batch_layout",
     "aco_batch_setup", "aco_batch_iterate", "aco_run_batched", "aco_features_workspace_bytes",
     "aco_edge_features", "aco_mlp_forward", "aco_mlp_backward_workspace_bytes",
-    "aco_mlp_backward", "aco_mlp_adam", "aco_tour_edge_labels",
+    "aco_mlp_backward", "aco_mlp_adam", "aco_tour_edge_labels", "aco_construct_partial",
+    "aco_update_local_best",
 )
 ACO_MLP_PARAMS = 4801
 ACO_MLP_OUT_LOGIT = 0
@@ -105,6 +106,9 @@ def lib():
             "aco_mlp_adam": (C.c_int, [p, p, p, p, i32, C.c_float, C.c_float, C.c_float,
                                        C.c_float, p]),
             "aco_tour_edge_labels": (C.c_int, [i32, i32, p, p, p, p, p]),
+            "aco_construct_partial": (C.c_int, [p, i32, i32, p, p, p, p, p, i32, i32, dbl, u64,
+                                                i64, dbl, i32, p, p, p, p, p, p, sz, p]),
+            "aco_update_local_best": (C.c_int, [i32, i32, p, p, p, p, p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -223,6 +227,29 @@ def aco_run(xy, n, params: AcoParams, best_tour, best_len, iter_best, tau_out, w
         _ptr(xy, torch.int32, "xy"), n, C.byref(params), _ptr(best_tour, torch.int32, "best_tour"),
         _ptr(best_len, torch.int64, "best_len"), _ptr(iter_best, torch.int64, "iter_best"),
         _ptr(tau_out, torch.float32, "tau_out"), _ptr(ws, torch.uint8, "ws"), ws.numel(),
+        _stream(stream)))
+
+
+def aco_construct_partial(xy, n, k, nn, nnd, eta_b, grid, tau, m, ant0, alpha, seed, iteration,
+                          p_partial, max_modify, lbest, tours, lengths, slots, step_prob, ws,
+                          stream=None):
+    torch = _t()
+    _check(lib().aco_construct_partial(
+        _ptr(xy, torch.int32, "xy"), n, k, _ptr(nn, torch.int32, "nn"),
+        _ptr(nnd, torch.int32, "nnd"), _ptr(eta_b, torch.float32, "eta_b"),
+        _ptr(grid, torch.uint8, "grid"), _ptr(tau, torch.float32, "tau"), m, ant0, float(alpha),
+        int(seed), int(iteration), float(p_partial), int(max_modify),
+        _ptr(lbest, torch.int32, "lbest"), _ptr(tours, torch.int32, "tours"),
+        _ptr(lengths, torch.int64, "lengths"), _ptr(slots, torch.uint8, "slots"),
+        _ptr(step_prob, torch.float32, "step_prob"), _ptr(ws, torch.uint8, "ws"), ws.numel(),
+        _stream(stream)))
+
+
+def aco_update_local_best(n, m, tours, lengths, lbest, lbest_len, stream=None):
+    torch = _t()
+    _check(lib().aco_update_local_best(
+        n, m, _ptr(tours, torch.int32, "tours"), _ptr(lengths, torch.int64, "lengths"),
+        _ptr(lbest, torch.int32, "lbest"), _ptr(lbest_len, torch.int64, "lbest_len"),
         _stream(stream)))
 
 
@@ -355,6 +382,24 @@ class Colony:
         aco_construct_tours(self.xy, self.n, self.k, self.nn, self.nnd, self.eta_b, self.grid,
                             self.tau, m, ant0, self.alpha, self.seed, iteration, self.tours,
                             self.lengths, self.slots, self.step_prob, self.cws, stream)
+
+    def construct_partial(self, iteration, p_partial, max_modify, stream=None):
+        """PartialACO construction from the ants' local bests (`self.lbest`)."""
+        aco_construct_partial(self.xy, self.n, self.k, self.nn, self.nnd, self.eta_b, self.grid,
+                              self.tau, self.m, 0, self.alpha, self.seed, iteration, p_partial,
+                              max_modify, self.lbest, self.tours, self.lengths, self.slots,
+                              self.step_prob, self.cws, stream)
+
+    def update_local_best(self, stream=None):
+        """Take this iteration's tours into the local bests where strictly shorter
+        (allocates the local bests on first use)."""
+        torch = _t()
+        if getattr(self, "lbest", None) is None:
+            self.lbest = torch.empty((self.m, self.n), dtype=torch.int32, device=self.device)
+            self.lbest_len = torch.full((self.m,), 2**63 - 1, dtype=torch.int64,
+                                        device=self.device)
+        aco_update_local_best(self.n, self.m, self.tours, self.lengths, self.lbest,
+                              self.lbest_len, stream)
 
     def track_best(self, iter_best=None, stream=None):
         aco_track_best(self.n, self.m, self.tours, self.lengths, self.best_len, self.best_tour,

@@ -61,9 +61,17 @@ struct VisBits {
     __device__ __forceinline__ static size_t bytes(int64_t n) { return (size_t)((n + 31) / 32) * 4; }
     __device__ __forceinline__ uint32_t test(int c) const { return (w[c >> 5] >> (c & 31)) & 1u; }
     __device__ __forceinline__ void set(int c) const { atomicOr(&w[c >> 5], 1u << (c & 31)); }
+    __device__ __forceinline__ void unset(int c) const
+    {
+        atomicAnd(&w[c >> 5], ~(1u << (c & 31)));
+    }
     __device__ __forceinline__ void clear(int n, int lane) const
     {
         for (int i = lane; i < ((n + 31) >> 5); i += kWave) w[i] = 0u;
+    }
+    __device__ __forceinline__ void fill(int n, int lane) const
+    {
+        for (int i = lane; i < ((n + 31) >> 5); i += kWave) w[i] = ~0u;
     }
 };
 
@@ -73,10 +81,16 @@ struct VisBytes {
     __device__ __forceinline__ static size_t bytes(int64_t n) { return (size_t)((n + 3) & ~3); }
     __device__ __forceinline__ uint32_t test(int c) const { return b[c]; }
     __device__ __forceinline__ void set(int c) const { b[c] = 1; }
+    __device__ __forceinline__ void unset(int c) const { b[c] = 0; }
     __device__ __forceinline__ void clear(int n, int lane) const
     {
         uint32_t *w = (uint32_t *)b;
         for (int i = lane; i < ((n + 3) >> 2); i += kWave) w[i] = 0u;
+    }
+    __device__ __forceinline__ void fill(int n, int lane) const
+    {
+        uint32_t *w = (uint32_t *)b;
+        for (int i = lane; i < ((n + 3) >> 2); i += kWave) w[i] = 0x01010101u;
     }
 };
 
@@ -122,6 +136,12 @@ struct AntTask {
     int32_t *tour;         // [n] output
     uint8_t *slots;        // [n] output
     float *prob;           // [n] output or nullptr
+    // PartialACO (Section 3.1, Algorithm 1): the ant's local best tour (city
+    // indices) or nullptr for a full construction; the partial-modification
+    // threshold P = round(p 2^32) and the cap M on the rebuilt cities.
+    const int32_t *lbest = nullptr;
+    uint64_t p_threshold = 0;
+    int32_t max_modify = 0;
 };
 
 // Builds one ant's tour with the whole wave (Section 2, Eq. 1).  Lane r < k
@@ -142,29 +162,65 @@ __device__ void build_ant_impl(const AntTask &T, const Vis &vis, const GridFn &g
 {
     const int lane = lane_id();
     const int32_t n = T.n, k = T.k;
-    vis.clear(n, lane);
     auto visited = [&](int city) { return vis.test(city); };
 
     const GridView g = grid();              // read once: no state carried through the loop
     uint32_t rnd = colony_draw(T.seed, T.iteration, T.ant, (uint32_t)lane);
     const uint32_t x0 = (uint32_t)read_lane_i32((int32_t)rnd, 0);
-    const int32_t start_city = (int32_t)(((uint64_t)x0 * (uint64_t)n) >> 32);
-    const int32_t start = space.from_city(g, start_city);
-    if (lane == 0) vis.set(start);
-
     const bool active = lane < k;
     const int lr = active ? lane : k - 1;   // idle lanes re-read a valid element
-    int32_t c = start;
+
+    // PartialACO plan from words 0-2 of the block of step 0: keep the
+    // lbest[s], ..., lbest[s + keep - 1] (cyclic) and rebuild n - keep cities
+    int32_t keep = 0;
+    int64_t s_pos = 0;
+    if (T.lbest) {
+        const uint4 plan = philox_block(0u, T.ant, T.iteration, 0u, (uint32_t)T.seed,
+                                        (uint32_t)(T.seed >> 32));
+        if ((uint64_t)plan.y < T.p_threshold) {
+            const int64_t M = T.max_modify < 1 ? 1 : (T.max_modify > n - 1 ? n - 1 : T.max_modify);
+            const int64_t r = 1 + (int64_t)(((uint64_t)plan.z * (uint64_t)M) >> 32);
+            keep = (int32_t)(n - r);
+            s_pos = (int64_t)(((uint64_t)plan.x * (uint64_t)n) >> 32);
+        }
+    }
+    int32_t start, c;
+    if (keep == 0) {
+        vis.clear(n, lane);
+        start = space.from_city(g, (int32_t)(((uint64_t)x0 * (uint64_t)n) >> 32));
+        if (lane == 0) vis.set(start);
+        c = start;
+    } else {
+        // every city visited except the n - keep to rebuild; the kept part is
+        // copied to the tour (no construction record: slot kNoSlot)
+        // (a local best is a permutation; the range checks only keep a wrong
+        // one from turning into an out-of-bounds access)
+        vis.fill(n, lane);
+        for (int32_t j = lane; j < n - keep; j += kWave) {
+            const int32_t city = T.lbest[(s_pos + keep + j) % n];
+            if ((uint32_t)city < (uint32_t)n) vis.unset(space.from_city(g, city));
+        }
+        for (int32_t t = lane; t < keep; t += kWave) {
+            T.tour[t] = T.lbest[(s_pos + t) % n];
+            T.slots[t] = (uint8_t)kNoSlot;
+            if constexpr (kProb) T.prob[t] = 1.0f;
+        }
+        const int32_t last_kept = T.lbest[(s_pos + keep - 1) % n];
+        c = space.from_city(g, (uint32_t)last_kept < (uint32_t)n ? last_kept : 0);
+        start = c;
+    }
+    const int32_t first = keep == 0 ? 1 : keep;   // first constructed tour position
+    const int32_t store_from = keep;             // positions written by the step loop
 
     CandW e = T.rows[(int64_t)c * k + lr];
-    for (int32_t base = 0; base < n; base += kWave) {
+    for (int32_t base = first & ~(kWave - 1); base < n; base += kWave) {
         if (base > 0) rnd = colony_draw(T.seed, T.iteration, T.ant, (uint32_t)(base + lane));
         // staged outputs: lane l holds step base + l (step 0 is the start city)
         int32_t st_city = start;
         uint32_t st_slot = kNoSlot;
         float st_prob = 1.0f;
         const int32_t last = min(base + kWave - 1, n - 1);
-        for (int32_t step = max(base, 1); step <= last; ++step) {
+        for (int32_t step = max(base, first); step <= last; ++step) {
             const int idx = step - base;
             const int32_t j = e.city;
             const uint32_t seen = visited(j);          // every lane reads a valid word
@@ -215,7 +271,7 @@ __device__ void build_ant_impl(const AntTask &T, const Vis &vis, const GridFn &g
             }
             c = jn;
         }
-        if (base + lane <= last) {
+        if (base + lane <= last && base + lane >= store_from) {
             T.tour[base + lane] = space.to_city(g, st_city);
             T.slots[base + lane] = (uint8_t)st_slot;
             if constexpr (kProb) T.prob[base + lane] = st_prob;

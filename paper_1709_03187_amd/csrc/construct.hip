@@ -45,6 +45,9 @@ struct ConstructArgs {
     int64_t *lengths;
     uint8_t *slots;
     float *step_prob;
+    const int32_t *lbest;   // [m][n] local best tours (PartialACO) or nullptr
+    uint64_t p_threshold;
+    int32_t max_modify;
 };
 
 // One ant per workgroup of one wave; the visited bitmask is the workgroup's LDS.
@@ -64,6 +67,9 @@ __global__ __launch_bounds__(kWave) void k_construct(ConstructArgs A)
     T.tour = A.tours + (int64_t)a * A.n;
     T.slots = A.slots + (int64_t)a * A.n;
     T.prob = A.step_prob ? A.step_prob + (int64_t)a * A.n : nullptr;
+    T.lbest = A.lbest ? A.lbest + (int64_t)a * A.n : nullptr;
+    T.p_threshold = A.p_threshold;
+    T.max_modify = A.max_modify;
     build_ant<KP>(T, VisBits{vis}, [&]() { return grid_view(A.grid); }, PositionSpace());
     if (lane_id() == 0) A.lengths[a] = 0;       // summed by k_tour_length
 }
@@ -108,14 +114,13 @@ extern "C" size_t aco_construct_workspace_bytes(int32_t n, int32_t k)
     return (size_t)n * (size_t)k * sizeof(CandW);
 }
 
-extern "C" int aco_construct_tours(const int32_t *xy, int32_t n, int32_t k, const int32_t *nn,
-                                   const int32_t *nnd, const float *eta_b, const void *grid,
-                                   const float *tau, int32_t m, int32_t ant0, double alpha,
-                                   uint64_t seed, int64_t iteration, int32_t *tours,
-                                   int64_t *lengths, uint8_t *slots, float *step_prob, void *ws,
-                                   size_t ws_bytes, void *stream)
+static int construct(const int32_t *xy, int32_t n, int32_t k, const int32_t *nn,
+                     const int32_t *nnd, const float *eta_b, const void *grid, const float *tau,
+                     int32_t m, int32_t ant0, double alpha, uint64_t seed, int64_t iteration,
+                     const int32_t *lbest, uint64_t p_threshold, int32_t max_modify,
+                     int32_t *tours, int64_t *lengths, uint8_t *slots, float *step_prob,
+                     void *ws, size_t ws_bytes, void *stream)
 {
-    clear_error();
     ACO_REQUIRE(n >= 3 && n <= (1 << 27), "n = %d out of range [3, 2^27]", n);
     ACO_REQUIRE(k >= 1 && k <= ACO_MAX_K && k <= n - 1, "k = %d out of range", k);
     ACO_REQUIRE(m >= 1 && ant0 >= 0 && (int64_t)ant0 + m <= INT32_MAX, "bad ant range");
@@ -145,8 +150,9 @@ extern "C" int aco_construct_tours(const int32_t *xy, int32_t n, int32_t k, cons
     if (lds > 65536)
         ACO_HIP_CHECK(hipFuncSetAttribute((const void *)kern,
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    ConstructArgs A{xy, rows, grid, n, k, ant0, (uint32_t)iteration, seed,
-                    tours, lengths, slots, step_prob};
+    ConstructArgs A{xy,    rows,    grid,      n,     k,           ant0,
+                    (uint32_t)iteration,       seed,      tours, lengths, slots,
+                    step_prob, lbest,   p_threshold, max_modify};
     kern<<<m, kWave, lds, st>>>(A);
     ACO_LAUNCH_CHECK("k_construct");
     const int32_t chunks = (n + kLenThreads - 1) / kLenThreads;
@@ -154,4 +160,35 @@ extern "C" int aco_construct_tours(const int32_t *xy, int32_t n, int32_t k, cons
         xy, tours, n, chunks, (unsigned long long *)lengths);
     ACO_LAUNCH_CHECK("k_tour_length");
     return ACO_OK;
+}
+
+extern "C" int aco_construct_tours(const int32_t *xy, int32_t n, int32_t k, const int32_t *nn,
+                                   const int32_t *nnd, const float *eta_b, const void *grid,
+                                   const float *tau, int32_t m, int32_t ant0, double alpha,
+                                   uint64_t seed, int64_t iteration, int32_t *tours,
+                                   int64_t *lengths, uint8_t *slots, float *step_prob, void *ws,
+                                   size_t ws_bytes, void *stream)
+{
+    clear_error();
+    return construct(xy, n, k, nn, nnd, eta_b, grid, tau, m, ant0, alpha, seed, iteration,
+                     nullptr, 0, 0, tours, lengths, slots, step_prob, ws, ws_bytes, stream);
+}
+
+extern "C" int aco_construct_partial(const int32_t *xy, int32_t n, int32_t k, const int32_t *nn,
+                                     const int32_t *nnd, const float *eta_b, const void *grid,
+                                     const float *tau, int32_t m, int32_t ant0, double alpha,
+                                     uint64_t seed, int64_t iteration, double p_partial,
+                                     int32_t max_modify, const int32_t *lbest, int32_t *tours,
+                                     int64_t *lengths, uint8_t *slots, float *step_prob,
+                                     void *ws, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    ACO_REQUIRE(lbest, "lbest is NULL");
+    ACO_REQUIRE(std::isfinite(p_partial) && p_partial >= 0.0 && p_partial <= 1.0,
+                "p_partial = %g out of [0, 1]", p_partial);
+    ACO_REQUIRE(max_modify >= 1, "max_modify = %d must be >= 1", max_modify);
+    // P = round(p 2^32), ties to even (the current rounding mode)
+    const uint64_t thr = (uint64_t)std::nearbyint(std::ldexp(p_partial, 32));
+    return construct(xy, n, k, nn, nnd, eta_b, grid, tau, m, ant0, alpha, seed, iteration, lbest,
+                     thr, max_modify, tours, lengths, slots, step_prob, ws, ws_bytes, stream);
 }

@@ -12,11 +12,11 @@ constexpr uint32_t kNoSlot = 255;
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy
 // as 1, 2, 3", SC'11).  Ten rounds of the two-multiply S-box; the key advances
-// by the Weyl constants after every round.  Only word 0 of the output block is
-// needed by the colony.
+// by the Weyl constants after every round.  The colony uses word 0 of each
+// step's block; a PartialACO plan uses words 0-2 of the block of step 0.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t philox_word0(uint32_t c0, uint32_t c1, uint32_t c2,
-                                                 uint32_t c3, uint32_t k0, uint32_t k1)
+__device__ __forceinline__ uint4 philox_block(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                              uint32_t k0, uint32_t k1)
 {
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
@@ -33,7 +33,13 @@ __device__ __forceinline__ uint32_t philox_word0(uint32_t c0, uint32_t c1, uint3
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
-    return c0;
+    return make_uint4(c0, c1, c2, c3);
+}
+
+__device__ __forceinline__ uint32_t philox_word0(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                 uint32_t c3, uint32_t k0, uint32_t k1)
+{
+    return philox_block(c0, c1, c2, c3, k0, k1).x;
 }
 
 // Word for (seed, iteration, ant, step): counter (step, ant, iteration, 0).

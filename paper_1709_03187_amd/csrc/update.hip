@@ -155,6 +155,25 @@ __global__ __launch_bounds__(256) void k_best_finish(const int64_t *__restrict__
     }
 }
 
+// PartialACO local bests (Algorithm 1): ant a's row is replaced when its new
+// tour is strictly shorter.  The copy reads lbest_len, the second kernel then
+// updates it, so every block of the copy sees the old value.
+__global__ void k_lbest_copy(const int32_t *__restrict__ tours, const int64_t *__restrict__ lengths,
+                             int32_t n, int32_t a0, const int64_t *__restrict__ lbest_len,
+                             int32_t *__restrict__ lbest)
+{
+    const int32_t a = a0 + (int32_t)blockIdx.y;
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n || lengths[a] >= lbest_len[a]) return;
+    lbest[(int64_t)a * n + t] = tours[(int64_t)a * n + t];
+}
+
+__global__ void k_lbest_len(const int64_t *__restrict__ lengths, int32_t m, int64_t *lbest_len)
+{
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a < m && lengths[a] < lbest_len[a]) lbest_len[a] = lengths[a];
+}
+
 }  // namespace aco
 
 using namespace aco;
@@ -211,5 +230,25 @@ extern "C" int aco_track_best(int32_t n, int32_t m, const int32_t *tours, const 
                                                                     best_len, best_tour);
     k_best_finish<<<1, 256, 0, st>>>(lengths, m, best_len, iter_best);
     ACO_LAUNCH_CHECK("best tracking");
+    return ACO_OK;
+}
+
+extern "C" int aco_update_local_best(int32_t n, int32_t m, const int32_t *tours,
+                                     const int64_t *lengths, int32_t *lbest, int64_t *lbest_len,
+                                     void *stream)
+{
+    clear_error();
+    ACO_REQUIRE(n >= 3 && n <= (1 << 27), "n = %d out of range [3, 2^27]", n);
+    ACO_REQUIRE(m >= 1, "m = %d must be >= 1", m);
+    ACO_REQUIRE(tours && lengths && lbest && lbest_len, "NULL array argument");
+    hipStream_t st = as_stream(stream);
+    for (int32_t a0 = 0; a0 < m; a0 += 65535) {
+        const int32_t ma = m - a0 < 65535 ? m - a0 : 65535;
+        k_lbest_copy<<<dim3(blocks_for(n, 256), (unsigned)ma), 256, 0, st>>>(tours, lengths, n, a0,
+                                                                          lbest_len, lbest);
+    }
+    ACO_LAUNCH_CHECK("k_lbest_copy");
+    k_lbest_len<<<blocks_for(m, 256), 256, 0, st>>>(lengths, m, lbest_len);
+    ACO_LAUNCH_CHECK("k_lbest_len");
     return ACO_OK;
 }
