@@ -10,12 +10,14 @@ Prints one JSON line.  `value` = ant-steps per second over whole iterations,
 m * (n - 1) ant-steps per iteration.  `roofline` prices the construction
 kernel by its algorithmic bytes per ant-step.  `cpu_baseline` times the CPU
 oracle (threads over ants) on a fixed sample of ants of the same workload.
-Two further objects report the batched colonies (4,096 instances, one
-persistent launch, autotuned) and the learned heuristic (training on the GPU,
-kernel rates, and the equal-wall-clock comparison with plain eta).
+Further objects report the batched colonies (4,096 instances, one
+persistent launch, autotuned), the learned heuristic (training on the GPU,
+kernel rates, and the equal-wall-clock comparison with plain eta) and
+PartialACO (rebuilding at most 1% of each ant's local best per iteration,
+run for the plain colony's wall time).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                    [--no-batched] [--no-learned]
+                    [--no-batched] [--no-learned] [--no-partial]
 """
 from __future__ import annotations
 
@@ -259,6 +261,64 @@ def learned_block(xy_eval, cfg):
     }
 
 
+def partial_block(xy, cfg, budget_s):
+    """PartialACO (Section 3.1, Algorithm 1) on the evaluation workload with
+    the paper's 1% cap at 200K cities and p = 1: iteration 0 builds full
+    tours (the local bests); every later iteration each ant rebuilds at most
+    n/100 cities of its local best.  Reports the time of a partial iteration
+    (construction + local bests + pheromone update), the rebuilt ant-steps per
+    second, and the best tour reached within `budget_s` seconds (the plain
+    colony's run time) from set-up."""
+    import torch
+
+    import paper_1709_03187_amd as aco
+    n = cfg["n"]
+    M = max(1, n // 100)
+    col = aco.Colony(xy=xy, k=cfg["k"], m=cfg["m"], alpha=cfg["alpha"], beta=cfg["beta"],
+                     rho=cfg["rho"], seed=cfg["seed"])
+    torch.cuda.synchronize()
+    t0 = time.time()
+    col.setup()
+    col.construct(0)
+    col.update_local_best()
+    col.track_best()
+    col.update()
+    torch.cuda.synchronize()
+    first_s = time.time() - t0
+    stream = torch.cuda.current_stream()
+    its = 1
+    ev = []
+    while True:
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        t_it = time.time()
+        e[0].record(stream)
+        col.construct_partial(its, 1.0, M)
+        e[1].record(stream)
+        col.update_local_best()
+        col.track_best()
+        e[2].record(stream)
+        col.update()
+        e[3].record(stream)
+        torch.cuda.synchronize()
+        ev.append(e)
+        its += 1
+        if time.time() + (time.time() - t_it) > t0 + budget_s:
+            break
+    con = np.array([x[0].elapsed_time(x[1]) for x in ev])
+    it_ms = np.array([x[0].elapsed_time(x[3]) for x in ev])
+    # rebuilt steps per ant: E[r] = (M + 1) / 2
+    steps = cfg["m"] * (M + 1) / 2
+    res = {"cap": M, "p_partial": 1.0, "iterations": its, "seconds": time.time() - t0,
+           "first_full_iteration_s": first_s,
+           "ms_per_partial_iteration": float(it_ms.mean()),
+           "construct_partial_ms": float(con.mean()),
+           "rebuilt_ant_steps_per_s": steps / (con.mean() * 1e-3),
+           "best_len": int(col.best_len.item()), "L_nn": col.L_nn}
+    del col
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -268,6 +328,7 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-partial", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -394,6 +455,11 @@ def main():
     if not args.no_learned:
         log("[bench] learned heuristic: training and equal-time comparison")
         out["learned"] = learned_block(xy, cfg)
+    if not args.no_partial:
+        log("[bench] PartialACO at the 1% cap")
+        gpu_time = t_cand + t_init + wall_warm + wall
+        out["partial"] = partial_block(xy, cfg, gpu_time)
+        out["partial"]["plain_best_len_same_time"] = best_len
     if not args.no_cpu_baseline:
         threads = args.cpu_threads or max(1, min(16, os.cpu_count() or 1))
         log(f"[bench] cpu baseline with {threads} threads")

@@ -200,10 +200,26 @@ __device__ void build_ant_impl(const AntTask &T, const Vis &vis, const GridFn &g
             const int32_t city = T.lbest[(s_pos + keep + j) % n];
             if ((uint32_t)city < (uint32_t)n) vis.unset(space.from_city(g, city));
         }
-        for (int32_t t = lane; t < keep; t += kWave) {
-            T.tour[t] = T.lbest[(s_pos + t) % n];
-            T.slots[t] = (uint8_t)kNoSlot;
-            if constexpr (kProb) T.prob[t] = 1.0f;
+        // copy eight positions per lane per round, loads issued before stores
+        constexpr int kU = 8;
+        for (int32_t t0 = 0; t0 < keep; t0 += kU * kWave) {
+            int32_t v[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int32_t t = t0 + u * kWave + lane;
+                int64_t q = s_pos + t;
+                q -= q >= n ? n : 0;
+                v[u] = t < keep ? T.lbest[q] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int32_t t = t0 + u * kWave + lane;
+                if (t < keep) {
+                    T.tour[t] = v[u];
+                    T.slots[t] = (uint8_t)kNoSlot;
+                    if constexpr (kProb) T.prob[t] = 1.0f;
+                }
+            }
         }
         const int32_t last_kept = T.lbest[(s_pos + keep - 1) % n];
         c = space.from_city(g, (uint32_t)last_kept < (uint32_t)n ? last_kept : 0);
