@@ -41,6 +41,8 @@ PINS = {
     "update": "pure-evaporation closed form; numpy float32 merge; integer conservation; symmetry",
     "partial (PartialACO)": "p=0 equals the full construction; r=1 gives the rotated local best; "
                             "exact rational completion probabilities (n=7); plan statistics",
+    "pheromone_local_best": "closed form for one tour; exact rational weights; conservation; "
+                            "order invariance; the global best's weight is 2^shift",
 }
 
 
@@ -85,6 +87,8 @@ def lib():
             "oracle_run": (C.c_int, [i64, C.c_int, p, i64, dbl, dbl, dbl, i64, u64, C.c_int,
                                      C.c_int, p, p, p, p]),
             "oracle_partial_plan": (None, [u64, i64, i64, i64, u64, i64, p, p, p]),
+            "oracle_pheromone_local_best": (None, [i64, C.c_int, p, i64, p, p, dbl, dbl,
+                                                   C.c_int, p, p]),
             "oracle_construct_partial": (None, [i64, C.c_int, p, p, p, p, p, dbl, dbl, u64, i64,
                                                 p, i64, p, u64, i64, p, p, p, p]),
             "oracle_replay_partial": (None, [i64, C.c_int, p, p, p, p, p, dbl, dbl, u64, i64, i64,
@@ -310,6 +314,20 @@ def replay_partial(xy, nn, nnd, tau, alpha, beta, seed, iteration, ant, lbest, p
     res = {f: int(out[i]) for i, f in enumerate(REPLAY_FIELDS)}
     res["kept"] = int(out[7])
     return res, prob
+
+
+def pheromone_local_best(nn, lbest, lbest_len, tau_base, delta, shift=32):
+    """Pheromone from the local best tours (P-ACO variant, Section 3).
+    Returns (tau float32 [n][k], q int64 [m])."""
+    nn = np.ascontiguousarray(nn, np.int32)
+    lbest = np.ascontiguousarray(lbest, np.int32)
+    lbest_len = np.ascontiguousarray(lbest_len, np.int64)
+    n, k = nn.shape
+    tau = np.empty((n, k), np.float32)
+    q = np.empty(len(lbest_len), np.int64)
+    lib().oracle_pheromone_local_best(n, k, _p(nn), len(lbest_len), _p(lbest), _p(lbest_len),
+                                      float(tau_base), float(delta), int(shift), _p(tau), _p(q))
+    return tau, q
 
 
 def update_local_best(lbest, lbest_len, tours, lengths):

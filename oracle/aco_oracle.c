@@ -456,6 +456,43 @@ void oracle_replay_ant(const colony_t *C, int64_t ant, const int32_t *tour, doub
 }
 
 /* ------------------------------------------------------------------ */
+/* Pheromone from the ants' local best tours (the P-ACO variant of        */
+/* Section 3): no evaporation; an edge of ant a's local best contributes  */
+/* the quality ratio w_a = L_g / L_a in (0, 1], L_g the shortest local    */
+/* best, so tau = tau_base + delta * sum of w_a over the local bests that */
+/* use the edge.  w_a is quantised as q_a = floor(2^shift * w_a) with the */
+/* ratio in FP64; tau = fl32(base + fl32(fl32(acc) * fl32(delta 2^-shift))).*/
+/* ------------------------------------------------------------------ */
+
+static void deposit_quanta(int64_t n, int k, const int32_t *nn, int64_t m, const int32_t *tours,
+                           const int64_t *qa, int64_t *acc);
+
+void oracle_pheromone_local_best(int64_t n, int k, const int32_t *nn, int64_t m,
+                                 const int32_t *lbest, const int64_t *lbest_len, double tau_base,
+                                 double delta, int shift, float *tau, int64_t *q_out)
+{
+    int64_t Lg = lbest_len[0];
+    for (int64_t a = 1; a < m; a++)
+        if (lbest_len[a] < Lg) Lg = lbest_len[a];
+    int64_t *q = (int64_t *)malloc((size_t)m * sizeof(int64_t));
+    for (int64_t a = 0; a < m; a++) {
+        double ratio = (double)Lg / (double)lbest_len[a];
+        q[a] = (int64_t)floor(ldexp(ratio, shift));
+        if (q_out) q_out[a] = q[a];
+    }
+    int64_t *acc = (int64_t *)malloc((size_t)(n * k) * sizeof(int64_t));
+    deposit_quanta(n, k, nn, m, lbest, q, acc);
+    float base = (float)tau_base;
+    float scale = (float)(delta * ldexp(1.0, -shift));
+    for (int64_t e = 0; e < n * k; e++) {
+        float dep = (float)acc[e] * scale;
+        tau[e] = base + dep;
+    }
+    free(acc);
+    free(q);
+}
+
+/* ------------------------------------------------------------------ */
 /* PartialACO (Section 3.1, Algorithm 1): each ant keeps a random part   */
 /* of its local best tour and rebuilds the rest.  The plan of ant a at   */
 /* an iteration comes from the Philox block at counter (0, a, iteration):*/
@@ -589,6 +626,24 @@ void oracle_replay_partial(int64_t n, int k, const int32_t *xy, const int32_t *n
 /* Each undirected edge {i,j} is stored as up to two directed slots      */
 /* (j in nn[i], i in nn[j]); both get the deposit, absent slots nothing. */
 /* ------------------------------------------------------------------ */
+
+/* acc = sum over tours a of q[a] on both directed slots of every tour edge */
+static void deposit_quanta(int64_t n, int k, const int32_t *nn, int64_t m, const int32_t *tours,
+                           const int64_t *qa, int64_t *acc)
+{
+    memset(acc, 0, (size_t)(n * k) * sizeof(int64_t));
+    for (int64_t a = 0; a < m; a++) {
+        int64_t q = qa[a];
+        const int32_t *T = tours + a * n;
+        for (int64_t t = 0; t < n; t++) {
+            int64_t i = T[t], j = T[(t + 1) % n];
+            for (int r = 0; r < k; r++)
+                if (nn[i * k + r] == j) acc[i * k + r] += q;
+            for (int r = 0; r < k; r++)
+                if (nn[j * k + r] == i) acc[j * k + r] += q;
+        }
+    }
+}
 
 void oracle_deposit(int64_t n, int k, const int32_t *nn, int64_t m, const int32_t *tours,
                     const int64_t *lengths, int shift, int64_t *acc)

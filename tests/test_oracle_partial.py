@@ -123,3 +123,49 @@ def test_local_best_replaced_only_when_strictly_shorter():
     nb, nl = orc.update_local_best(lb, lbl, tours, lengths)
     np.testing.assert_array_equal(nb, np.stack([tours[0], lb[1], lb[2]]))
     np.testing.assert_array_equal(nl, [9, 20, 30])
+
+
+# ---------------------------------------------------------------- local-best pheromone
+def _tour_slots(nn, tour):
+    """Boolean [n][k]: slots (i, r) whose edge {i, nn[i][r]} is an edge of the tour."""
+    n, k = nn.shape
+    nxt = np.empty(n, np.int64)
+    prv = np.empty(n, np.int64)
+    t = np.asarray(tour, np.int64)
+    nxt[t] = np.roll(t, -1)
+    prv[t] = np.roll(t, 1)
+    return (nn == nxt[:, None]) | (nn == prv[:, None])
+
+
+def test_local_best_pheromone_one_tour_closed_form():
+    xy, nn, nnd, tau = _instance(300, 8, 21)
+    lb, lbl = _local_bests(xy, nn, nnd, tau, 1, 3)
+    t, q = orc.pheromone_local_best(nn, lb, lbl, 0.5, 0.25)
+    assert q[0] == 2**32                       # the global best itself has weight 1
+    on = _tour_slots(nn, lb[0])
+    assert on.any() and not on.all()
+    np.testing.assert_array_equal(t[on], np.float32(0.75))
+    np.testing.assert_array_equal(t[~on], np.float32(0.5))
+
+
+def test_local_best_pheromone_weights_and_order():
+    xy, nn, nnd, tau = _instance(300, 8, 22)
+    lb, lbl = _local_bests(xy, nn, nnd, tau, 6, 4)
+    t, q = orc.pheromone_local_best(nn, lb, lbl, 1.0 / 299, 1.0 / 6, shift=40)
+    Lg = int(lbl.min())
+    for a in range(6):
+        exact_q = Fraction(Lg * 2**40, int(lbl[a]))
+        assert abs(q[a] - exact_q) <= 1 and q[a] <= 2**40
+    assert q[int(np.argmin(lbl))] == 2**40
+    # the sum over ants does not depend on their order (integer accumulation)
+    perm = np.array([3, 0, 5, 1, 4, 2])
+    t2, _ = orc.pheromone_local_best(nn, lb[perm], lbl[perm], 1.0 / 299, 1.0 / 6, shift=40)
+    np.testing.assert_array_equal(t.view(np.uint32), t2.view(np.uint32))
+    # slots on no local best keep the base level; the others are above it
+    on = np.zeros_like(nn, bool)
+    for a in range(6):
+        on |= _tour_slots(nn, lb[a])
+    np.testing.assert_array_equal(t[~on], np.float32(1.0 / 299))
+    assert (t[on] > np.float32(1.0 / 299)).all()
+    # an edge used by every local best at weight ~1 carries about base + delta * m
+    assert t.max() <= np.float32(1.0 / 299 + 1.0) * (1 + 1e-6)
