@@ -284,6 +284,23 @@ int aco_construct_partial(const int32_t *xy, int32_t n, int32_t k, const int32_t
 int aco_update_local_best(int32_t n, int32_t m, const int32_t *tours, const int64_t *lengths,
                           int32_t *lbest, int64_t *lbest_len, void *stream);
 
+/* Pheromone from the ants' local best tours (the P-ACO variant of Section 3:
+ * no evaporation; an edge of ant a's local best contributes the quality
+ * ratio w_a = L_g / L_a in (0, 1], L_g the shortest local best):
+ *     tau[i][r] = tau_base + delta * sum of w_a over the local bests that use
+ *                 the edge {i, nn[i][r]}.
+ * w_a is quantised as q_a = floor(2^shift * w_a) with the ratio in FP64 and
+ * summed exactly in int64; tau = fl32(fl32(tau_base) + fl32(fl32(acc) *
+ * fl32(delta * 2^-shift))), both directed slots of an edge equal.
+ *   lbest int32 [m][n], lbest_len int64 [m] (> 0); tau float [n][k] (output)
+ *   ws  aco_update_workspace_bytes(n, k, m) bytes
+ * Errors: INVALID_ARG (sizes, shift outside [0, 62], tau_base or delta < 0 or
+ * not finite), WORKSPACE. */
+int aco_pheromone_local_best(int32_t n, int32_t k, const int32_t *nn, const int8_t *rev,
+                             int32_t m, const int32_t *lbest, const int64_t *lbest_len,
+                             double tau_base, double delta, int32_t deposit_shift, float *tau,
+                             void *ws, size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------------------------
  * Learned heuristic.  A small network scores every candidate edge from its
  * local geometry, and sigmoid(score) replaces eta = 1/d in the weights

@@ -38,7 +38,7 @@ EXPORTS = (
     "aco_batch_setup", "aco_batch_iterate", "aco_run_batched", "aco_features_workspace_bytes",
     "aco_edge_features", "aco_mlp_forward", "aco_mlp_backward_workspace_bytes",
     "aco_mlp_backward", "aco_mlp_adam", "aco_tour_edge_labels", "aco_construct_partial",
-    "aco_update_local_best",
+    "aco_update_local_best", "aco_pheromone_local_best",
 )
 ACO_MLP_PARAMS = 4801
 ACO_MLP_OUT_LOGIT = 0
@@ -109,6 +109,8 @@ def lib():
             "aco_construct_partial": (C.c_int, [p, i32, i32, p, p, p, p, p, i32, i32, dbl, u64,
                                                 i64, dbl, i32, p, p, p, p, p, p, sz, p]),
             "aco_update_local_best": (C.c_int, [i32, i32, p, p, p, p, p]),
+            "aco_pheromone_local_best": (C.c_int, [i32, i32, p, p, i32, p, p, dbl, dbl, i32, p, p,
+                                                   sz, p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -251,6 +253,16 @@ def aco_update_local_best(n, m, tours, lengths, lbest, lbest_len, stream=None):
         n, m, _ptr(tours, torch.int32, "tours"), _ptr(lengths, torch.int64, "lengths"),
         _ptr(lbest, torch.int32, "lbest"), _ptr(lbest_len, torch.int64, "lbest_len"),
         _stream(stream)))
+
+
+def aco_pheromone_local_best(n, k, nn, rev, m, lbest, lbest_len, tau_base, delta, deposit_shift,
+                             tau, ws, stream=None):
+    torch = _t()
+    _check(lib().aco_pheromone_local_best(
+        n, k, _ptr(nn, torch.int32, "nn"), _ptr(rev, torch.int8, "rev"), m,
+        _ptr(lbest, torch.int32, "lbest"), _ptr(lbest_len, torch.int64, "lbest_len"),
+        float(tau_base), float(delta), int(deposit_shift), _ptr(tau, torch.float32, "tau"),
+        _ptr(ws, torch.uint8, "ws"), ws.numel(), _stream(stream)))
 
 
 # ------------------------------------------------------------ learned heuristic
@@ -400,6 +412,12 @@ class Colony:
                                         device=self.device)
         aco_update_local_best(self.n, self.m, self.tours, self.lengths, self.lbest,
                               self.lbest_len, stream)
+
+    def pheromone_from_local_best(self, tau_base, delta, stream=None):
+        """tau from the local best tours (no evaporation), replacing the table."""
+        aco_pheromone_local_best(self.n, self.k, self.nn, self.rev, self.m, self.lbest,
+                                 self.lbest_len, tau_base, delta, self.deposit_shift, self.tau,
+                                 self.uws, stream)
 
     def track_best(self, iter_best=None, stream=None):
         aco_track_best(self.n, self.m, self.tours, self.lengths, self.best_len, self.best_tour,

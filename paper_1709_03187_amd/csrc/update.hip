@@ -155,6 +155,37 @@ __global__ __launch_bounds__(256) void k_best_finish(const int64_t *__restrict__
     }
 }
 
+// Pheromone from the local best tours (the P-ACO variant of Section 3): the
+// quantum of local best a is q_a = floor(2^shift * L_g / L_a) with the ratio
+// in FP64 and L_g the shortest local best (one workgroup).
+__global__ __launch_bounds__(1024) void k_quanta_ratio(const int64_t *__restrict__ lbest_len,
+                                                       int32_t m, int32_t shift,
+                                                       int64_t *__restrict__ q)
+{
+    __shared__ int64_t red[1024 / kWave];
+    int64_t lmin = INT64_MAX;
+    for (int a = threadIdx.x; a < m; a += blockDim.x) lmin = lbest_len[a] < lmin ? lbest_len[a] : lmin;
+    const int64_t Lg = block_min_i64(lmin, red);
+    for (int a = threadIdx.x; a < m; a += blockDim.x)
+        q[a] = (int64_t)floor(ldexp((double)Lg / (double)lbest_len[a], shift));
+}
+
+// tau = fl32(base + fl32(fl32(acc) * scale)), no evaporation; the canonical
+// slot rule as in k_merge.
+__global__ void k_merge_base(float *__restrict__ tau, const int64_t *__restrict__ acc,
+                             const int32_t *__restrict__ nn, const int8_t *__restrict__ rev,
+                             int32_t k, int64_t count, float base, float scale)
+{
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = (count <= INT32_MAX) ? (int64_t)((uint32_t)e / (uint32_t)k) : e / k;
+        const int32_t j = nn[e];
+        const int r2 = rev[e];
+        const int64_t src = (r2 >= 0 && j < i) ? (int64_t)j * k + r2 : e;
+        tau[e] = __fadd_rn(base, __fmul_rn((float)acc[src], scale));
+    }
+}
+
 // PartialACO local bests (Algorithm 1): ant a's row is replaced when its new
 // tour is strictly shorter.  The copy reads lbest_len, the second kernel then
 // updates it, so every block of the copy sees the old value.
@@ -250,5 +281,42 @@ extern "C" int aco_update_local_best(int32_t n, int32_t m, const int32_t *tours,
     ACO_LAUNCH_CHECK("k_lbest_copy");
     k_lbest_len<<<blocks_for(m, 256), 256, 0, st>>>(lengths, m, lbest_len);
     ACO_LAUNCH_CHECK("k_lbest_len");
+    return ACO_OK;
+}
+
+extern "C" int aco_pheromone_local_best(int32_t n, int32_t k, const int32_t *nn,
+                                        const int8_t *rev, int32_t m, const int32_t *lbest,
+                                        const int64_t *lbest_len, double tau_base, double delta,
+                                        int32_t deposit_shift, float *tau, void *ws,
+                                        size_t ws_bytes, void *stream)
+{
+    clear_error();
+    ACO_REQUIRE(n >= 3 && n <= (1 << 27), "n = %d out of range [3, 2^27]", n);
+    ACO_REQUIRE(k >= 1 && k <= ACO_MAX_K && k <= n - 1, "k = %d out of range", k);
+    ACO_REQUIRE(m >= 1, "m = %d must be >= 1", m);
+    ACO_REQUIRE(deposit_shift >= 0 && deposit_shift <= 62, "deposit_shift = %d out of [0, 62]",
+                deposit_shift);
+    ACO_REQUIRE(std::isfinite(tau_base) && tau_base >= 0.0 && std::isfinite(delta) && delta >= 0.0,
+                "tau_base and delta must be finite and >= 0");
+    ACO_REQUIRE(nn && rev && lbest && lbest_len && tau && ws, "NULL array argument");
+    const size_t need = aco_update_workspace_bytes(n, k, m);
+    if (ws_bytes < need)
+        return fail(ACO_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    hipStream_t st = as_stream(stream);
+    const int64_t nk = (int64_t)n * k;
+    int64_t *acc = (int64_t *)ws;
+    int64_t *q = (int64_t *)((char *)ws + (size_t)nk * 8);
+    k_zero_i64<<<std::min(4096u, blocks_for(nk, 256)), 256, 0, st>>>(acc, nk);
+    k_quanta_ratio<<<1, 1024, 0, st>>>(lbest_len, m, deposit_shift, q);
+    for (int32_t a0 = 0; a0 < m; a0 += 65535) {
+        const int32_t ma = m - a0 < 65535 ? m - a0 : 65535;
+        k_deposit<<<dim3(blocks_for(n, 256), (unsigned)ma), 256, 0, st>>>(
+            nn, rev, n, k, a0, lbest, nullptr, q, (unsigned long long *)acc);
+    }
+    const float base = (float)tau_base;
+    const float scale = (float)(delta * std::ldexp(1.0, -deposit_shift));
+    k_merge_base<<<std::min(4096u, blocks_for(nk, 256)), 256, 0, st>>>(tau, acc, nn, rev, k, nk,
+                                                                      base, scale);
+    ACO_LAUNCH_CHECK("local-best pheromone");
     return ACO_OK;
 }

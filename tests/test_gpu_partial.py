@@ -178,3 +178,34 @@ def test_partial_rejects_bad_arguments():
     with pytest.raises(aco.AcoError):
         col.construct_partial(1, 0.5, 10)
     col.lbest = saved
+
+
+def test_partial_with_local_best_pheromone():
+    """PartialACO on the P-ACO pheromone (Section 3): after every iteration the
+    table is recomputed from the local bests, bit-exactly as the oracle does;
+    the next iteration is replayed on it."""
+    xy = instances.make_coords("c1")
+    k, m, seed, M = 10, 32, 8, 150
+    n = len(xy)
+    base, delta = 1.0 / (n - 1), 1.0 / m
+    col = colony(xy, k=k, m=m, seed=seed, want_prob=True)
+    col.setup()
+    nn, nnd = orc.knn_rows(xy, k, threads=threads())
+    col.construct(0)
+    col.update_local_best()
+    lbest, lbest_len = _np(col.lbest).copy(), _np(col.lbest_len).copy()
+    col.pheromone_from_local_best(base, delta)
+    tau, q = orc.pheromone_local_best(nn, lbest, lbest_len, base, delta)
+    np.testing.assert_array_equal(_np(col.tau), tau)
+    for it in range(1, 5):
+        say(f"[partial] local-best pheromone iteration {it}")
+        col.construct_partial(it, 0.95, M)
+        tours, lengths = _np(col.tours), _np(col.lengths)
+        check_partial(xy, nn, nnd, tau, seed, it, lbest, 0.95, M, tours, lengths, _np(col.slots),
+                      _np(col.step_prob), range(m), f"pbest it={it}")
+        col.update_local_best()
+        lbest, lbest_len = orc.update_local_best(lbest, lbest_len, tours, lengths)
+        np.testing.assert_array_equal(_np(col.lbest), lbest)
+        col.pheromone_from_local_best(base, delta)
+        tau, q = orc.pheromone_local_best(nn, lbest, lbest_len, base, delta)
+        np.testing.assert_array_equal(_np(col.tau), tau, err_msg=f"it={it}")
