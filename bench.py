@@ -261,14 +261,17 @@ def learned_block(xy_eval, cfg):
     }
 
 
-def partial_block(xy, cfg, budget_s):
+def partial_block(xy, cfg, budget_s, pheromone_kind="table"):
     """PartialACO (Section 3.1, Algorithm 1) on the evaluation workload with
     the paper's 1% cap at 200K cities and p = 1: iteration 0 builds full
     tours (the local bests); every later iteration each ant rebuilds at most
     n/100 cities of its local best.  Reports the time of a partial iteration
     (construction + local bests + pheromone update), the rebuilt ant-steps per
     second, and the best tour reached within `budget_s` seconds (the plain
-    colony's run time) from set-up."""
+    colony's run time) from set-up.  pheromone_kind="table": the n x k table with
+    evaporation and the iteration's deposits; "local_best": recomputed each
+    iteration from the ants' local bests (the paper's P-ACO variant, base
+    1/(n-1), delta 1/m)."""
     import torch
 
     import paper_1709_03187_amd as aco
@@ -279,12 +282,21 @@ def partial_block(xy, cfg, budget_s):
     torch.cuda.synchronize()
     t0 = time.time()
     col.setup()
+    base, delta = 1.0 / (n - 1), 1.0 / cfg["m"]
+
+    def pheromone():
+        if pheromone_kind == "table":
+            col.update()
+        else:
+            col.pheromone_from_local_best(base, delta)
+
     col.construct(0)
     col.update_local_best()
     col.track_best()
-    col.update()
+    pheromone()
     torch.cuda.synchronize()
     first_s = time.time() - t0
+    lb_first = float(col.lbest_len.double().mean().item())
     stream = torch.cuda.current_stream()
     its = 1
     ev = []
@@ -297,7 +309,7 @@ def partial_block(xy, cfg, budget_s):
         col.update_local_best()
         col.track_best()
         e[2].record(stream)
-        col.update()
+        pheromone()
         e[3].record(stream)
         torch.cuda.synchronize()
         ev.append(e)
@@ -308,12 +320,14 @@ def partial_block(xy, cfg, budget_s):
     it_ms = np.array([x[0].elapsed_time(x[3]) for x in ev])
     # rebuilt steps per ant: E[r] = (M + 1) / 2
     steps = cfg["m"] * (M + 1) / 2
-    res = {"cap": M, "p_partial": 1.0, "iterations": its, "seconds": time.time() - t0,
+    res = {"pheromone": pheromone_kind, "cap": M, "p_partial": 1.0, "iterations": its, "seconds": time.time() - t0,
            "first_full_iteration_s": first_s,
            "ms_per_partial_iteration": float(it_ms.mean()),
            "construct_partial_ms": float(con.mean()),
            "rebuilt_ant_steps_per_s": steps / (con.mean() * 1e-3),
-           "best_len": int(col.best_len.item()), "L_nn": col.L_nn}
+           "best_len": int(col.best_len.item()), "L_nn": col.L_nn,
+           "mean_local_best_first": lb_first,
+           "mean_local_best_last": float(col.lbest_len.double().mean().item())}
     del col
     torch.cuda.empty_cache()
     return res
@@ -460,6 +474,8 @@ def main():
         gpu_time = t_cand + t_init + wall_warm + wall
         out["partial"] = partial_block(xy, cfg, gpu_time)
         out["partial"]["plain_best_len_same_time"] = best_len
+        log("[bench] PartialACO on local-best pheromone")
+        out["partial_local_best_pheromone"] = partial_block(xy, cfg, gpu_time, "local_best")
     if not args.no_cpu_baseline:
         threads = args.cpu_threads or max(1, min(16, os.cpu_count() or 1))
         log(f"[bench] cpu baseline with {threads} threads")
