@@ -90,9 +90,9 @@ def lib():
             "oracle_pheromone_local_best": (None, [i64, C.c_int, p, i64, p, p, dbl, dbl,
                                                    C.c_int, p, p]),
             "oracle_construct_partial": (None, [i64, C.c_int, p, p, p, p, p, dbl, dbl, u64, i64,
-                                                p, i64, p, u64, i64, p, p, p, p]),
+                                                p, i64, p, u64, i64, C.c_int, p, p, p, p]),
             "oracle_replay_partial": (None, [i64, C.c_int, p, p, p, p, p, dbl, dbl, u64, i64, i64,
-                                             p, u64, i64, p, dbl, p, p]),
+                                             p, u64, i64, C.c_int, p, dbl, p, p]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(L, name)
@@ -270,10 +270,14 @@ def partial_plan(seed, iteration, ant, n, p, max_modify):
     return int(s.value), bool(part.value), int(r.value)
 
 
+SAMPLER_ROULETTE = 0      # Eq. 1
+SAMPLER_INDEPENDENT = 1   # Independent Roulette (Section 3)
+
+
 def construct_partial(xy, nn, nnd, tau, alpha, beta, seed, iteration, ants, lbest, p, max_modify,
-                      eta=None):
-    """PartialACO construction of the listed ants; lbest [len(ants)][n] are their local bests.
-    Returns dict(tours, lengths, slots, probs)."""
+                      eta=None, sampler=SAMPLER_ROULETTE):
+    """PartialACO construction of the listed ants; lbest [len(ants)][n] are their local bests
+    (p = 0: full tours).  Returns dict(tours, lengths, slots, probs)."""
     xy = _xy(xy)
     n = len(xy)
     nn = np.ascontiguousarray(nn, np.int32)
@@ -289,13 +293,13 @@ def construct_partial(xy, nn, nnd, tau, alpha, beta, seed, iteration, ants, lbes
     probs = np.empty((A, n), np.float64)
     lib().oracle_construct_partial(n, nn.shape[1], _p(xy), _p(nn), _p(nnd), _p(tau), _p(eta),
                                    float(alpha), float(beta), int(seed), int(iteration), _p(ants),
-                                   A, _p(lbest), p_threshold(p), int(max_modify), _p(tours),
-                                   _p(lengths), _p(slots), _p(probs))
+                                   A, _p(lbest), p_threshold(p), int(max_modify), int(sampler),
+                                   _p(tours), _p(lengths), _p(slots), _p(probs))
     return dict(tours=tours, lengths=lengths, slots=slots, probs=probs)
 
 
 def replay_partial(xy, nn, nnd, tau, alpha, beta, seed, iteration, ant, lbest, p, max_modify,
-                   tour, eta=None, boundary_eps=1e-6):
+                   tour, eta=None, boundary_eps=1e-6, sampler=SAMPLER_ROULETTE):
     """Teacher-forced replay of a PartialACO tour.  Returns (counts dict with 'kept', prob)."""
     xy = _xy(xy)
     n = len(xy)
@@ -309,8 +313,8 @@ def replay_partial(xy, nn, nnd, tau, alpha, beta, seed, iteration, ant, lbest, p
     out = np.zeros(8, np.int64)
     lib().oracle_replay_partial(n, nn.shape[1], _p(xy), _p(nn), _p(nnd), _p(tau), _p(eta),
                                 float(alpha), float(beta), int(seed), int(iteration), int(ant),
-                                _p(lbest), p_threshold(p), int(max_modify), _p(tour),
-                                float(boundary_eps), _p(prob), _p(out))
+                                _p(lbest), p_threshold(p), int(max_modify), int(sampler),
+                                _p(tour), float(boundary_eps), _p(prob), _p(out))
     res = {f: int(out[i]) for i, f in enumerate(REPLAY_FIELDS)}
     res["kept"] = int(out[7])
     return res, prob

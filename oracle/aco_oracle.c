@@ -292,6 +292,7 @@ typedef struct {
     double alpha, beta;
     uint64_t seed;
     int64_t iteration;
+    int sampler;             /* 0: roulette of Eq. 1; 1: Independent Roulette (Section 3) */
 } colony_t;
 
 /* Heuristic eta_ir = 1/d_ir (Section 2); d = 0 (coincident cities) is read as 1. */
@@ -341,6 +342,49 @@ static int roulette(const colony_t *C, const double *w, const double *cum, doubl
     return last;
 }
 
+/* Independent Roulette (Section 3): every unvisited candidate r with w_r > 0
+ * gets its own uniform U_r and the largest w_r * U_r (FP64) wins, ties to
+ * the lower rank.  U_r = x * 2^-32, x = word (r mod 4) of the Philox block at
+ * counter (t, ant, iteration, 1 + r / 4) (word 3 of the roulette's counter is
+ * 0, so the two never share a draw).  *v_best and *v_second receive the two
+ * largest products. */
+static double ir_uniform(const colony_t *C, int64_t ant, int64_t t, int r)
+{
+    uint32_t ctr[4] = {(uint32_t)t, (uint32_t)ant, (uint32_t)C->iteration, 1u + (uint32_t)(r / 4)};
+    uint32_t key[2] = {(uint32_t)C->seed, (uint32_t)(C->seed >> 32)};
+    uint32_t out[4];
+    oracle_philox4x32_10(ctr, key, out);
+    return (double)out[r % 4] * 0x1p-32;
+}
+
+static int independent_roulette(const colony_t *C, int64_t ant, int64_t t, const double *w,
+                                double *v_best, double *v_second, double *v_of)
+{
+    int best = -1;
+    double vb = -1.0, vs = -1.0;
+    for (int r = 0; r < C->k; r++) {
+        v_of[r] = -1.0;
+        if (w[r] <= 0.0) continue;
+        double v = w[r] * ir_uniform(C, ant, t, r);
+        v_of[r] = v;
+        if (v > vb) { vs = vb; vb = v; best = r; }
+        else if (v > vs) vs = v;
+    }
+    *v_best = vb;
+    *v_second = vs;
+    return best;
+}
+
+/* The slot chosen at tour position t with draw u (roulette) or the step's
+ * independent uniforms (Independent Roulette). */
+static int select_slot(const colony_t *C, int64_t ant, int64_t t, const double *w,
+                       const double *cum, double S, double u)
+{
+    if (C->sampler == 0) return roulette(C, w, cum, S, u);
+    double vb, vs, v_of[64];
+    return independent_roulette(C, ant, t, w, &vb, &vs, v_of);
+}
+
 typedef struct {
     int64_t length;
     int64_t fallbacks;
@@ -368,7 +412,7 @@ static ant_result_t construct_ant(const colony_t *C, int64_t ant, int32_t *tour,
         double S = row_weights(C, c, vis, w, cum, &nu);
         int64_t j, d;
         if (nu > 0 && S > 0.0) {
-            int r = roulette(C, w, cum, S, u);
+            int r = select_slot(C, ant, t, w, cum, S, u);
             j = C->nn[c * k + r];
             d = C->nnd[c * k + r];
             if (slot) slot[t] = (int8_t)r;
@@ -422,14 +466,25 @@ static void replay_from(const colony_t *C, int64_t ant, const int32_t *tour, int
         int nu;
         double S = row_weights(C, c, vis, w, cum, &nu);
         if (nu > 0 && S > 0.0) {
-            int r = roulette(C, w, cum, S, u);
             int taken = -1;
             for (int q = 0; q < k; q++)
                 if (C->nn[c * k + q] == j) taken = q;
             prob[t] = (taken >= 0) ? w[taken] / S : 0.0;
-            int near = 0;
-            for (int q = 0; q < k; q++)
-                if (w[q] > 0.0 && fabs(u - cum[q] / S) < boundary_eps) near = 1;
+            int r, near = 0;
+            if (C->sampler == 0) {
+                r = roulette(C, w, cum, S, u);
+                for (int q = 0; q < k; q++)
+                    if (w[q] > 0.0 && fabs(u - cum[q] / S) < boundary_eps) near = 1;
+            } else {
+                /* a near tie: the top two products within 2^-22 of each other
+                 * (the GPU's weights are the FP64 weights rounded once to FP32) */
+                double vb, vs, v_of[64];
+                r = independent_roulette(C, ant, t, w, &vb, &vs, v_of);
+                if (vs >= 0.0 && vb - vs <= 0x1p-22 * vb) near = 1;
+                if (taken >= 0 && taken != r && v_of[taken] >= 0.0 &&
+                    vb - v_of[taken] > 0x1p-22 * vb) near = 0;
+                prob[t] = (taken >= 0 && v_of[taken] >= 0.0) ? v_of[taken] / vb : 0.0;
+            }
             if (near) out[6]++;
             if (taken != r) {
                 if (near && taken >= 0 && w[taken] > 0.0) out[2]++;
@@ -549,7 +604,7 @@ static ant_result_t construct_partial_ant(const colony_t *C, int64_t ant, const 
         double S = row_weights(C, c, vis, w, cum, &nu);
         int64_t j, d;
         if (nu > 0 && S > 0.0) {
-            int q = roulette(C, w, cum, S, u);
+            int q = select_slot(C, ant, t, w, cum, S, u);
             j = C->nn[c * k + q];
             d = C->nnd[c * k + q];
             if (slot) slot[t] = (int8_t)q;
@@ -574,12 +629,13 @@ void oracle_construct_partial(int64_t n, int k, const int32_t *xy, const int32_t
                               const int32_t *nnd, const float *tau, const double *eta,
                               double alpha, double beta, uint64_t seed, int64_t iteration,
                               const int64_t *ants, int64_t count, const int32_t *lbest,
-                              uint64_t p_threshold, int64_t max_modify, int32_t *tours,
-                              int64_t *lengths, int8_t *slots, double *probs)
+                              uint64_t p_threshold, int64_t max_modify, int sampler,
+                              int32_t *tours, int64_t *lengths, int8_t *slots, double *probs)
 {
     colony_t C;
     C.n = n; C.k = k; C.xy = xy; C.nn = nn; C.nnd = nnd; C.tau = tau; C.eta = eta;
     C.alpha = alpha; C.beta = beta; C.seed = seed; C.iteration = iteration;
+    C.sampler = sampler;
     for (int64_t q = 0; q < count; q++) {
         ant_result_t r = construct_partial_ant(&C, ants[q], lbest + q * n, p_threshold,
                                                max_modify, tours + q * n,
@@ -598,11 +654,13 @@ void oracle_replay_partial(int64_t n, int k, const int32_t *xy, const int32_t *n
                            const int32_t *nnd, const float *tau, const double *eta, double alpha,
                            double beta, uint64_t seed, int64_t iteration, int64_t ant,
                            const int32_t *lbest, uint64_t p_threshold, int64_t max_modify,
-                           const int32_t *tour, double boundary_eps, double *prob, int64_t *out)
+                           int sampler, const int32_t *tour, double boundary_eps, double *prob,
+                           int64_t *out)
 {
     colony_t C;
     C.n = n; C.k = k; C.xy = xy; C.nn = nn; C.nnd = nnd; C.tau = tau; C.eta = eta;
     C.alpha = alpha; C.beta = beta; C.seed = seed; C.iteration = iteration;
+    C.sampler = sampler;
     int64_t s, r;
     int partial;
     oracle_partial_plan(seed, iteration, ant, n, p_threshold, max_modify, &s, &partial, &r);
@@ -718,6 +776,7 @@ static void colony_init(colony_t *C, int64_t n, int k, const int32_t *xy, const 
 {
     C->n = n; C->k = k; C->xy = xy; C->nn = nn; C->nnd = nnd; C->tau = tau; C->eta = eta;
     C->alpha = alpha; C->beta = beta; C->seed = seed; C->iteration = iteration;
+    C->sampler = 0;
 }
 
 /* Construct the ants listed in `ants` (count of them); outputs are [count][n]. */
