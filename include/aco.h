@@ -276,6 +276,33 @@ int aco_construct_partial(const int32_t *xy, int32_t n, int32_t k, const int32_t
                           const int32_t *lbest, int32_t *tours, int64_t *lengths, uint8_t *slots,
                           float *step_prob, void *ws, size_t ws_bytes, void *stream);
 
+/* Construction with options: the sampler of the next city and PartialACO.
+ *   sampler ACO_SAMPLER_ROULETTE: Eq. 1 as in aco_construct_tours;
+ *           ACO_SAMPLER_INDEPENDENT: Independent Roulette (Section 3): among
+ *           the unvisited candidates with positive weight the largest
+ *           w_r * U_r (FP64) wins, ties to the lower rank; U_r = x * 2^-32 with
+ *           x word (r mod 4) of the Philox block at counter
+ *           (t, ant, iteration, 1 + r / 4).  Its move probabilities are not
+ *           computed: step_prob must be NULL.
+ *   lbest   NULL for full tours, else PartialACO with p_partial and
+ *           max_modify as in aco_construct_partial.
+ * opts is a host pointer (NULL: roulette, full tours).  Other arguments and
+ * errors as aco_construct_tours. */
+#define ACO_SAMPLER_ROULETTE 0
+#define ACO_SAMPLER_INDEPENDENT 1
+typedef struct aco_construct_opts {
+    int32_t sampler;
+    double p_partial;
+    int32_t max_modify;
+    const int32_t *lbest;
+} aco_construct_opts_t;
+
+int aco_construct_ex(const int32_t *xy, int32_t n, int32_t k, const int32_t *nn,
+                     const int32_t *nnd, const float *eta_b, const void *grid, const float *tau,
+                     int32_t m, int32_t ant0, double alpha, uint64_t seed, int64_t iteration,
+                     const aco_construct_opts_t *opts, int32_t *tours, int64_t *lengths,
+                     uint8_t *slots, float *step_prob, void *ws, size_t ws_bytes, void *stream);
+
 /* Local bests (Algorithm 1): for every ant a with lengths[a] < lbest_len[a],
  * lbest[a] = tours[a] and lbest_len[a] = lengths[a] (strict improvement).
  * Initialise lbest_len to INT64_MAX to take the first tours.

@@ -38,8 +38,10 @@ EXPORTS = (
     "aco_batch_setup", "aco_batch_iterate", "aco_run_batched", "aco_features_workspace_bytes",
     "aco_edge_features", "aco_mlp_forward", "aco_mlp_backward_workspace_bytes",
     "aco_mlp_backward", "aco_mlp_adam", "aco_tour_edge_labels", "aco_construct_partial",
-    "aco_update_local_best", "aco_pheromone_local_best",
+    "aco_update_local_best", "aco_pheromone_local_best", "aco_construct_ex",
 )
+ACO_SAMPLER_ROULETTE = 0
+ACO_SAMPLER_INDEPENDENT = 1
 ACO_MLP_PARAMS = 4801
 ACO_MLP_OUT_LOGIT = 0
 ACO_MLP_OUT_ETA_B = 1
@@ -57,6 +59,11 @@ class AcoParams(C.Structure):
     _fields_ = [("m", C.c_int32), ("k", C.c_int32), ("alpha", C.c_double),
                 ("beta", C.c_double), ("rho", C.c_double), ("iterations", C.c_int32),
                 ("deposit_shift", C.c_int32), ("seed", C.c_uint64)]
+
+
+class AcoConstructOpts(C.Structure):
+    _fields_ = [("sampler", C.c_int32), ("p_partial", C.c_double), ("max_modify", C.c_int32),
+                ("lbest", C.c_void_p)]
 
 
 class AcoBatchLayout(C.Structure):
@@ -111,6 +118,8 @@ def lib():
             "aco_update_local_best": (C.c_int, [i32, i32, p, p, p, p, p]),
             "aco_pheromone_local_best": (C.c_int, [i32, i32, p, p, i32, p, p, dbl, dbl, i32, p, p,
                                                    sz, p]),
+            "aco_construct_ex": (C.c_int, [p, i32, i32, p, p, p, p, p, i32, i32, dbl, u64, i64,
+                                           C.POINTER(AcoConstructOpts), p, p, p, p, p, sz, p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -242,6 +251,22 @@ def aco_construct_partial(xy, n, k, nn, nnd, eta_b, grid, tau, m, ant0, alpha, s
         _ptr(grid, torch.uint8, "grid"), _ptr(tau, torch.float32, "tau"), m, ant0, float(alpha),
         int(seed), int(iteration), float(p_partial), int(max_modify),
         _ptr(lbest, torch.int32, "lbest"), _ptr(tours, torch.int32, "tours"),
+        _ptr(lengths, torch.int64, "lengths"), _ptr(slots, torch.uint8, "slots"),
+        _ptr(step_prob, torch.float32, "step_prob"), _ptr(ws, torch.uint8, "ws"), ws.numel(),
+        _stream(stream)))
+
+
+def aco_construct_ex(xy, n, k, nn, nnd, eta_b, grid, tau, m, ant0, alpha, seed, iteration, sampler,
+                     p_partial, max_modify, lbest, tours, lengths, slots, step_prob, ws,
+                     stream=None):
+    torch = _t()
+    opts = AcoConstructOpts(int(sampler), float(p_partial), int(max_modify),
+                            None if lbest is None else _ptr(lbest, torch.int32, "lbest").value)
+    _check(lib().aco_construct_ex(
+        _ptr(xy, torch.int32, "xy"), n, k, _ptr(nn, torch.int32, "nn"),
+        _ptr(nnd, torch.int32, "nnd"), _ptr(eta_b, torch.float32, "eta_b"),
+        _ptr(grid, torch.uint8, "grid"), _ptr(tau, torch.float32, "tau"), m, ant0, float(alpha),
+        int(seed), int(iteration), C.byref(opts), _ptr(tours, torch.int32, "tours"),
         _ptr(lengths, torch.int64, "lengths"), _ptr(slots, torch.uint8, "slots"),
         _ptr(step_prob, torch.float32, "step_prob"), _ptr(ws, torch.uint8, "ws"), ws.numel(),
         _stream(stream)))
@@ -401,6 +426,16 @@ class Colony:
                               self.tau, self.m, 0, self.alpha, self.seed, iteration, p_partial,
                               max_modify, self.lbest, self.tours, self.lengths, self.slots,
                               self.step_prob, self.cws, stream)
+
+    def construct_ex(self, iteration, sampler=ACO_SAMPLER_ROULETTE, p_partial=0.0, max_modify=1,
+                     partial=False, stream=None):
+        """Construction with a chosen sampler; partial=True rebuilds from the local bests."""
+        aco_construct_ex(self.xy, self.n, self.k, self.nn, self.nnd, self.eta_b, self.grid,
+                         self.tau, self.m, 0, self.alpha, self.seed, iteration, sampler,
+                         p_partial, max_modify, self.lbest if partial else None, self.tours,
+                         self.lengths, self.slots,
+                         self.step_prob if sampler == ACO_SAMPLER_ROULETTE else None, self.cws,
+                         stream)
 
     def update_local_best(self, stream=None):
         """Take this iteration's tours into the local bests where strictly shorter

@@ -142,6 +142,10 @@ struct AntTask {
     const int32_t *lbest = nullptr;
     uint64_t p_threshold = 0;
     int32_t max_modify = 0;
+    // next-city sampler: 0 the roulette of Eq. 1, 1 Independent Roulette
+    // (Section 3: the largest w_r U_r, U_r from word r mod 4 of the Philox
+    // block at counter (t, ant, iteration, 1 + r / 4); ties to the lower rank)
+    int32_t sampler = 0;
 };
 
 // Builds one ant's tour with the whole wave (Section 2, Eq. 1).  Lane r < k
@@ -252,25 +256,45 @@ __device__ void build_ant_impl(const AntTask &T, const Vis &vis, const GridFn &g
                 eg = T.rows[(int64_t)guess * k + lr];
             }
             const double wv = live ? (double)e.w : 0.0;
-            const double cum = wave_incl_scan_f64(wv, KP);
-            const double S = read_lane_f64(cum, k - 1);
             int32_t jn;
             uint32_t slot;
             float prob = -1.0f;
-            if (S > 0.0) {
-                const uint32_t x = (uint32_t)read_lane_i32((int32_t)rnd, idx);
-                const double target = (double)x * 0x1p-32 * S;
-                const uint64_t hit = __builtin_amdgcn_ballot_w64(live && target < cum);
-                // first slot whose running sum passes the target; if rounding
-                // leaves none, the last slot that can be chosen
-                const int f = hit ? __ffsll((unsigned long long)hit) - 1
-                                  : 63 - __clzll((long long)any);
-                jn = read_lane_i32(j, f);
-                slot = (uint32_t)f;
-                if constexpr (kProb) prob = (float)(read_lane_f64(wv, f) / S);
+            if (T.sampler != 0) {
+                // Independent Roulette: the largest product wins
+                if (any) {
+                    const uint4 blk = philox_block((uint32_t)step, T.ant, T.iteration,
+                                                   1u + (uint32_t)(lane >> 2), (uint32_t)T.seed,
+                                                   (uint32_t)(T.seed >> 32));
+                    const int wd = lane & 3;
+                    const uint32_t xw = wd == 0 ? blk.x : wd == 1 ? blk.y : wd == 2 ? blk.z : blk.w;
+                    const double v = live ? wv * ((double)xw * 0x1p-32) : -1.0;
+                    const double vmax = read_lane_f64(wave_incl_max_f64(v, KP), k - 1);
+                    const uint64_t top = __builtin_amdgcn_ballot_w64(live && v == vmax);
+                    const int f = __ffsll((unsigned long long)top) - 1;
+                    jn = read_lane_i32(j, f);
+                    slot = (uint32_t)f;
+                } else {
+                    jn = space.fallback(g, T.xy, c, vis, visited);
+                    slot = kNoSlot;
+                }
             } else {
-                jn = space.fallback(g, T.xy, c, vis, visited);
-                slot = kNoSlot;
+                const double cum = wave_incl_scan_f64(wv, KP);
+                const double S = read_lane_f64(cum, k - 1);
+                if (S > 0.0) {
+                    const uint32_t x = (uint32_t)read_lane_i32((int32_t)rnd, idx);
+                    const double target = (double)x * 0x1p-32 * S;
+                    const uint64_t hit = __builtin_amdgcn_ballot_w64(live && target < cum);
+                    // first slot whose running sum passes the target; if rounding
+                    // leaves none, the last slot that can be chosen
+                    const int f = hit ? __ffsll((unsigned long long)hit) - 1
+                                      : 63 - __clzll((long long)any);
+                    jn = read_lane_i32(j, f);
+                    slot = (uint32_t)f;
+                    if constexpr (kProb) prob = (float)(read_lane_f64(wv, f) / S);
+                } else {
+                    jn = space.fallback(g, T.xy, c, vis, visited);
+                    slot = kNoSlot;
+                }
             }
             // a city index is always in range here; the clamp only keeps a logic
             // error from turning into an out-of-bounds access (tests see the tour)

@@ -48,6 +48,7 @@ struct ConstructArgs {
     const int32_t *lbest;   // [m][n] local best tours (PartialACO) or nullptr
     uint64_t p_threshold;
     int32_t max_modify;
+    int32_t sampler;
 };
 
 // One ant per workgroup of one wave; the visited bitmask is the workgroup's LDS.
@@ -70,6 +71,7 @@ __global__ __launch_bounds__(kWave) void k_construct(ConstructArgs A)
     T.lbest = A.lbest ? A.lbest + (int64_t)a * A.n : nullptr;
     T.p_threshold = A.p_threshold;
     T.max_modify = A.max_modify;
+    T.sampler = A.sampler;
     build_ant<KP>(T, VisBits{vis}, [&]() { return grid_view(A.grid); }, PositionSpace());
     if (lane_id() == 0) A.lengths[a] = 0;       // summed by k_tour_length
 }
@@ -118,8 +120,8 @@ static int construct(const int32_t *xy, int32_t n, int32_t k, const int32_t *nn,
                      const int32_t *nnd, const float *eta_b, const void *grid, const float *tau,
                      int32_t m, int32_t ant0, double alpha, uint64_t seed, int64_t iteration,
                      const int32_t *lbest, uint64_t p_threshold, int32_t max_modify,
-                     int32_t *tours, int64_t *lengths, uint8_t *slots, float *step_prob,
-                     void *ws, size_t ws_bytes, void *stream)
+                     int32_t sampler, int32_t *tours, int64_t *lengths, uint8_t *slots,
+                     float *step_prob, void *ws, size_t ws_bytes, void *stream)
 {
     ACO_REQUIRE(n >= 3 && n <= (1 << 27), "n = %d out of range [3, 2^27]", n);
     ACO_REQUIRE(k >= 1 && k <= ACO_MAX_K && k <= n - 1, "k = %d out of range", k);
@@ -152,7 +154,7 @@ static int construct(const int32_t *xy, int32_t n, int32_t k, const int32_t *nn,
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     ConstructArgs A{xy,    rows,    grid,      n,     k,           ant0,
                     (uint32_t)iteration,       seed,      tours, lengths, slots,
-                    step_prob, lbest,   p_threshold, max_modify};
+                    step_prob, lbest,   p_threshold, max_modify, sampler};
     kern<<<m, kWave, lds, st>>>(A);
     ACO_LAUNCH_CHECK("k_construct");
     const int32_t chunks = (n + kLenThreads - 1) / kLenThreads;
@@ -171,7 +173,8 @@ extern "C" int aco_construct_tours(const int32_t *xy, int32_t n, int32_t k, cons
 {
     clear_error();
     return construct(xy, n, k, nn, nnd, eta_b, grid, tau, m, ant0, alpha, seed, iteration,
-                     nullptr, 0, 0, tours, lengths, slots, step_prob, ws, ws_bytes, stream);
+                     nullptr, 0, 0, ACO_SAMPLER_ROULETTE, tours, lengths, slots, step_prob, ws,
+                     ws_bytes, stream);
 }
 
 extern "C" int aco_construct_partial(const int32_t *xy, int32_t n, int32_t k, const int32_t *nn,
@@ -190,5 +193,32 @@ extern "C" int aco_construct_partial(const int32_t *xy, int32_t n, int32_t k, co
     // P = round(p 2^32), ties to even (the current rounding mode)
     const uint64_t thr = (uint64_t)std::nearbyint(std::ldexp(p_partial, 32));
     return construct(xy, n, k, nn, nnd, eta_b, grid, tau, m, ant0, alpha, seed, iteration, lbest,
-                     thr, max_modify, tours, lengths, slots, step_prob, ws, ws_bytes, stream);
+                     thr, max_modify, ACO_SAMPLER_ROULETTE, tours, lengths, slots, step_prob, ws,
+                     ws_bytes, stream);
+}
+
+extern "C" int aco_construct_ex(const int32_t *xy, int32_t n, int32_t k, const int32_t *nn,
+                                const int32_t *nnd, const float *eta_b, const void *grid,
+                                const float *tau, int32_t m, int32_t ant0, double alpha,
+                                uint64_t seed, int64_t iteration, const aco_construct_opts_t *opts,
+                                int32_t *tours, int64_t *lengths, uint8_t *slots,
+                                float *step_prob, void *ws, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    aco_construct_opts_t o{ACO_SAMPLER_ROULETTE, 0.0, 0, nullptr};
+    if (opts) o = *opts;
+    ACO_REQUIRE(o.sampler == ACO_SAMPLER_ROULETTE || o.sampler == ACO_SAMPLER_INDEPENDENT,
+                "sampler = %d unknown", o.sampler);
+    ACO_REQUIRE(o.sampler == ACO_SAMPLER_ROULETTE || !step_prob,
+                "step_prob is only defined for the roulette sampler");
+    uint64_t thr = 0;
+    if (o.lbest) {
+        ACO_REQUIRE(std::isfinite(o.p_partial) && o.p_partial >= 0.0 && o.p_partial <= 1.0,
+                    "p_partial = %g out of [0, 1]", o.p_partial);
+        ACO_REQUIRE(o.max_modify >= 1, "max_modify = %d must be >= 1", o.max_modify);
+        thr = (uint64_t)std::nearbyint(std::ldexp(o.p_partial, 32));
+    }
+    return construct(xy, n, k, nn, nnd, eta_b, grid, tau, m, ant0, alpha, seed, iteration,
+                     o.lbest, thr, o.max_modify, o.sampler, tours, lengths, slots, step_prob, ws,
+                     ws_bytes, stream);
 }

@@ -124,6 +124,19 @@ __device__ __forceinline__ double wave_incl_scan_f64(double v, int width)
     return v;
 }
 
+// Inclusive running maximum with the same DPP pattern (lanes shifted in read
+// 0, which never exceeds a nonnegative value).
+__device__ __forceinline__ double wave_incl_max_f64(double v, int width)
+{
+    if (width > 1) v = fmax(v, dpp_f64<0x111, 0xF>(v));
+    if (width > 2) v = fmax(v, dpp_f64<0x112, 0xF>(v));
+    if (width > 4) v = fmax(v, dpp_f64<0x114, 0xF>(v));
+    if (width > 8) v = fmax(v, dpp_f64<0x118, 0xF>(v));
+    if (width > 16) v = fmax(v, dpp_f64<0x142, 0xA>(v));
+    if (width > 32) v = fmax(v, dpp_f64<0x143, 0xC>(v));
+    return v;
+}
+
 __device__ __forceinline__ int wave_incl_scan_i32(int v, int lane)
 {
 #pragma unroll
