@@ -261,7 +261,7 @@ def learned_block(xy_eval, cfg):
     }
 
 
-def partial_block(xy, cfg, budget_s, pheromone_kind="table"):
+def partial_block(xy, cfg, budget_s, pheromone_kind="table", sampler=0):
     """PartialACO (Section 3.1, Algorithm 1) on the evaluation workload with
     the paper's 1% cap at 200K cities and p = 1: iteration 0 builds full
     tours (the local bests); every later iteration each ant rebuilds at most
@@ -271,7 +271,7 @@ def partial_block(xy, cfg, budget_s, pheromone_kind="table"):
     colony's run time) from set-up.  pheromone_kind="table": the n x k table with
     evaporation and the iteration's deposits; "local_best": recomputed each
     iteration from the ants' local bests (the paper's P-ACO variant, base
-    1/(n-1), delta 1/m)."""
+    1/(n-1), delta 1/m).  sampler 1: Independent Roulette (Section 3)."""
     import torch
 
     import paper_1709_03187_amd as aco
@@ -290,7 +290,7 @@ def partial_block(xy, cfg, budget_s, pheromone_kind="table"):
         else:
             col.pheromone_from_local_best(base, delta)
 
-    col.construct(0)
+    col.construct_ex(0, sampler=sampler)
     col.update_local_best()
     col.track_best()
     pheromone()
@@ -304,7 +304,7 @@ def partial_block(xy, cfg, budget_s, pheromone_kind="table"):
         e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         t_it = time.time()
         e[0].record(stream)
-        col.construct_partial(its, 1.0, M)
+        col.construct_ex(its, sampler=sampler, p_partial=1.0, max_modify=M, partial=True)
         e[1].record(stream)
         col.update_local_best()
         col.track_best()
@@ -320,7 +320,7 @@ def partial_block(xy, cfg, budget_s, pheromone_kind="table"):
     it_ms = np.array([x[0].elapsed_time(x[3]) for x in ev])
     # rebuilt steps per ant: E[r] = (M + 1) / 2
     steps = cfg["m"] * (M + 1) / 2
-    res = {"pheromone": pheromone_kind, "cap": M, "p_partial": 1.0, "iterations": its, "seconds": time.time() - t0,
+    res = {"pheromone": pheromone_kind, "sampler": ["roulette", "independent"][sampler], "cap": M, "p_partial": 1.0, "iterations": its, "seconds": time.time() - t0,
            "first_full_iteration_s": first_s,
            "ms_per_partial_iteration": float(it_ms.mean()),
            "construct_partial_ms": float(con.mean()),
@@ -328,6 +328,36 @@ def partial_block(xy, cfg, budget_s, pheromone_kind="table"):
            "best_len": int(col.best_len.item()), "L_nn": col.L_nn,
            "mean_local_best_first": lb_first,
            "mean_local_best_last": float(col.lbest_len.double().mean().item())}
+    del col
+    torch.cuda.empty_cache()
+    return res
+
+
+def independent_block(xy, cfg, iterations=3):
+    """Full construction with Independent Roulette (Section 3) on the main
+    workload: construction time per iteration and ant-steps/s, next to the
+    roulette's."""
+    import torch
+
+    import paper_1709_03187_amd as aco
+    col = aco.Colony(xy=xy, k=cfg["k"], m=cfg["m"], alpha=cfg["alpha"], beta=cfg["beta"],
+                     rho=cfg["rho"], seed=cfg["seed"])
+    col.setup()
+    stream = torch.cuda.current_stream()
+    ms = []
+    for it in range(iterations + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        col.construct_ex(it, sampler=aco.ACO_SAMPLER_INDEPENDENT)
+        e1.record(stream)
+        col.track_best()
+        col.update()
+        torch.cuda.synchronize()
+        if it > 0:
+            ms.append(e0.elapsed_time(e1))
+    steps = cfg["m"] * (cfg["n"] - 1)
+    res = {"construct_ms": float(np.mean(ms)), "ant_steps_per_s": steps / (np.mean(ms) * 1e-3),
+           "iterations_timed": iterations, "best_len": int(col.best_len.item())}
     del col
     torch.cuda.empty_cache()
     return res
@@ -476,6 +506,10 @@ def main():
         out["partial"]["plain_best_len_same_time"] = best_len
         log("[bench] PartialACO on local-best pheromone")
         out["partial_local_best_pheromone"] = partial_block(xy, cfg, gpu_time, "local_best")
+        log("[bench] the paper's method: PartialACO + Independent Roulette + local-best pheromone")
+        out["partial_independent_local_best"] = partial_block(xy, cfg, gpu_time, "local_best", 1)
+        log("[bench] Independent Roulette, full tours")
+        out["independent_roulette"] = independent_block(xy, cfg)
     if not args.no_cpu_baseline:
         threads = args.cpu_threads or max(1, min(16, os.cpu_count() or 1))
         log(f"[bench] cpu baseline with {threads} threads")
