@@ -142,10 +142,6 @@ struct AntTask {
     const int32_t *lbest = nullptr;
     uint64_t p_threshold = 0;
     int32_t max_modify = 0;
-    // next-city sampler: 0 the roulette of Eq. 1, 1 Independent Roulette
-    // (Section 3: the largest w_r U_r, U_r from word r mod 4 of the Philox
-    // block at counter (t, ant, iteration, 1 + r / 4); ties to the lower rank)
-    int32_t sampler = 0;
 };
 
 // Builds one ant's tour with the whole wave (Section 2, Eq. 1).  Lane r < k
@@ -160,7 +156,7 @@ struct AntTask {
 // so the inner loop holds only the step itself.
 // KP is the scan width, the smallest power of two >= k.  `grid()` returns the
 // instance's GridView (used by fallback steps).
-template <int KP, bool kProb, class Space, class Vis, class GridFn>
+template <int KP, bool kProb, int kSampler, class Space, class Vis, class GridFn>
 __device__ void build_ant_impl(const AntTask &T, const Vis &vis, const GridFn &grid,
                                const Space &space)
 {
@@ -259,7 +255,7 @@ __device__ void build_ant_impl(const AntTask &T, const Vis &vis, const GridFn &g
             int32_t jn;
             uint32_t slot;
             float prob = -1.0f;
-            if (T.sampler != 0) {
+            if constexpr (kSampler != 0) {
                 // Independent Roulette: the largest product wins
                 if (any) {
                     const uint4 blk = philox_block((uint32_t)step, T.ant, T.iteration,
@@ -319,14 +315,18 @@ __device__ void build_ant_impl(const AntTask &T, const Vis &vis, const GridFn &g
     }
 }
 
-template <int KP, class Space = CitySpace, class Vis, class GridFn>
+// kSampler selects the next-city rule at compile time, so each kernel holds
+// one of them only: 0 the roulette of Eq. 1; 1 Independent Roulette (Section
+// 3: the largest w_r U_r, U_r from word r mod 4 of the Philox block at
+// counter (t, ant, iteration, 1 + r / 4), ties to the lower rank).
+template <int KP, class Space = CitySpace, int kSampler = 0, class Vis, class GridFn>
 __device__ void build_ant(const AntTask &T, const Vis &vis, const GridFn &grid,
                           const Space &space = Space())
 {
     if (T.prob)
-        build_ant_impl<KP, true>(T, vis, grid, space);
+        build_ant_impl<KP, true, kSampler>(T, vis, grid, space);
     else
-        build_ant_impl<KP, false>(T, vis, grid, space);
+        build_ant_impl<KP, false, kSampler>(T, vis, grid, space);
 }
 
 // The kx nearest cities of city `me` in (d, index) order, by one thread:

@@ -48,11 +48,11 @@ struct ConstructArgs {
     const int32_t *lbest;   // [m][n] local best tours (PartialACO) or nullptr
     uint64_t p_threshold;
     int32_t max_modify;
-    int32_t sampler;
 };
 
 // One ant per workgroup of one wave; the visited bitmask is the workgroup's LDS.
-template <int KP>
+// kSampler: 0 the roulette of Eq. 1, 1 Independent Roulette.
+template <int KP, int kSampler>
 __global__ __launch_bounds__(kWave) void k_construct(ConstructArgs A)
 {
     extern __shared__ uint32_t vis[];
@@ -71,8 +71,7 @@ __global__ __launch_bounds__(kWave) void k_construct(ConstructArgs A)
     T.lbest = A.lbest ? A.lbest + (int64_t)a * A.n : nullptr;
     T.p_threshold = A.p_threshold;
     T.max_modify = A.max_modify;
-    T.sampler = A.sampler;
-    build_ant<KP>(T, VisBits{vis}, [&]() { return grid_view(A.grid); }, PositionSpace());
+    build_ant<KP, PositionSpace, kSampler>(T, VisBits{vis}, [&]() { return grid_view(A.grid); });
     if (lane_id() == 0) A.lengths[a] = 0;       // summed by k_tour_length
 }
 
@@ -145,16 +144,19 @@ static int construct(const int32_t *xy, int32_t n, int32_t k, const int32_t *nn,
     k_choice_info<<<blocks_for(n, 256), 256, 0, st>>>(pts, pinv, nn, tau, eta_b, n, k, alpha,
                                                         rows);
     ACO_LAUNCH_CHECK("k_choice_info");
-    void (*kern)(ConstructArgs) = k <= 8    ? k_construct<8>
-                                  : k <= 16 ? k_construct<16>
-                                  : k <= 32 ? k_construct<32>
-                                            : k_construct<64>;
+    void (*kern)(ConstructArgs);
+    if (sampler == ACO_SAMPLER_INDEPENDENT)
+        kern = k <= 8 ? k_construct<8, 1> : k <= 16 ? k_construct<16, 1>
+             : k <= 32 ? k_construct<32, 1> : k_construct<64, 1>;
+    else
+        kern = k <= 8 ? k_construct<8, 0> : k <= 16 ? k_construct<16, 0>
+             : k <= 32 ? k_construct<32, 0> : k_construct<64, 0>;
     if (lds > 65536)
         ACO_HIP_CHECK(hipFuncSetAttribute((const void *)kern,
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     ConstructArgs A{xy,    rows,    grid,      n,     k,           ant0,
                     (uint32_t)iteration,       seed,      tours, lengths, slots,
-                    step_prob, lbest,   p_threshold, max_modify, sampler};
+                    step_prob, lbest,   p_threshold, max_modify};
     kern<<<m, kWave, lds, st>>>(A);
     ACO_LAUNCH_CHECK("k_construct");
     const int32_t chunks = (n + kLenThreads - 1) / kLenThreads;
