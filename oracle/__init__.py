@@ -93,6 +93,9 @@ def lib():
                                                 p, i64, p, u64, i64, C.c_int, p, p, p, p]),
             "oracle_replay_partial": (None, [i64, C.c_int, p, p, p, p, p, dbl, dbl, u64, i64, i64,
                                              p, u64, i64, C.c_int, p, dbl, p, p]),
+            "oracle_two_opt_selected": (C.c_int, [u64, i64, i64, u64]),
+            "oracle_two_opt_best": (None, [p, i64, p, i64, p, p]),
+            "oracle_two_opt": (i64, [p, i64, p, i64, i64, p, p, p]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(L, name)
@@ -318,6 +321,40 @@ def replay_partial(xy, nn, nnd, tau, alpha, beta, seed, iteration, ant, lbest, p
     res = {f: int(out[i]) for i, f in enumerate(REPLAY_FIELDS)}
     res["kept"] = int(out[7])
     return res, prob
+
+
+# ---------------------------------------------------------------- windowed 2-opt
+def two_opt_selected(seed, iteration, ant, p) -> bool:
+    """Does the ant's tour get 2-opt this iteration (word 3 of block (0, ant, iteration, 0)
+    below round(p 2^32))?"""
+    return bool(lib().oracle_two_opt_selected(int(seed), int(iteration), int(ant),
+                                               p_threshold(p)))
+
+
+def two_opt_best(xy, tour, window):
+    """Best improving move (gain < 0, ties to the smaller offset) of every position:
+    (gain[n], offset[n]); offset 0 where no move improves."""
+    xy = _xy(xy)
+    n = len(xy)
+    t = np.ascontiguousarray(tour, np.int32)
+    g = np.empty(n, np.int64)
+    o = np.empty(n, np.int64)
+    lib().oracle_two_opt_best(_p(xy), n, _p(t), int(window), _p(g), _p(o))
+    return g, o
+
+
+def two_opt(xy, tour, window, max_rounds=0):
+    """Windowed 2-opt of one tour (Sections 4-5), by rounds of non-overlapping best moves.
+    Returns (new tour, dict(rounds, moves, gain, converged))."""
+    xy = _xy(xy)
+    n = len(xy)
+    t = np.array(tour, np.int32)
+    mv, gn = C.c_int64(0), C.c_int64(0)
+    conv = C.c_int(0)
+    r = lib().oracle_two_opt(_p(xy), n, _p(t), int(window), int(max_rounds), C.byref(mv),
+                             C.byref(gn), C.byref(conv))
+    return t, dict(rounds=int(r), moves=int(mv.value), gain=int(gn.value),
+                   converged=bool(conv.value))
 
 
 def pheromone_local_best(nn, lbest, lbest_len, tau_base, delta, shift=32):

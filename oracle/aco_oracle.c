@@ -678,6 +678,133 @@ void oracle_replay_partial(int64_t n, int k, const int32_t *xy, const int32_t *n
 }
 
 /* ------------------------------------------------------------------ */
+/* Windowed 2-opt local search.  Section 4 applies 2-opt to a tour with */
+/* a small probability (0.001); Section 5 restricts it to pairs of tour */
+/* edges at most W = 500 positions apart.  The paper fixes neither the  */
+/* move order nor how the chosen tours are drawn; this is the reading:  */
+/*                                                                      */
+/* A tour takes part when word 3 of the Philox block at counter         */
+/* (0, ant, iteration, 0) is below P = round(p 2^32) (words 0-2 are the */
+/* start city and PartialACO's plan).                                   */
+/*                                                                      */
+/* Move (i, o), 2 <= o <= W' = min(W, n/2), positions mod n, j = i + o: */
+/* drop the edges (t_i, t_i+1) and (t_j, t_j+1), add (t_i, t_j) and     */
+/* (t_i+1, t_j+1), i.e. reverse t_i+1 .. t_j.  Its gain is              */
+/*   g = d(t_i, t_j) + d(t_i+1, t_j+1) - d(t_i, t_i+1) - d(t_j, t_j+1), */
+/* the change of the tour length.  It touches positions i .. j+1, its   */
+/* span.  One round: every position i takes its best move (the smallest */
+/* g < 0, ties to the smaller o); a position's move is applied when no  */
+/* other position's move with an overlapping span is better by (g, i).  */
+/* Applied spans are disjoint, so the moves commute and their gains     */
+/* add.  Rounds repeat until no position has a move with g < 0: the     */
+/* tour is then 2-optimal for every pair of edges within W positions.   */
+/* ------------------------------------------------------------------ */
+
+int oracle_two_opt_selected(uint64_t seed, int64_t iteration, int64_t ant, uint64_t p_threshold)
+{
+    uint32_t ctr[4] = {0u, (uint32_t)ant, (uint32_t)iteration, 0u};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t w[4];
+    oracle_philox4x32_10(ctr, key, w);
+    return (uint64_t)w[3] < p_threshold;
+}
+
+/* W' = min(W, floor(n/2)): a pair of edges o positions apart one way is   */
+/* n - o apart the other way, so it is taken once, from the nearer side    */
+/* (twice when o = n/2); o = n - 1 would pair adjacent edges.              */
+static int64_t two_opt_window(int64_t n, int64_t window)
+{
+    return window < n / 2 ? window : n / 2;
+}
+
+/* gain of move (i, o) on the tour, straight from the definition */
+static int64_t two_opt_gain(const int32_t *xy, int64_t n, const int32_t *t, int64_t i, int64_t o)
+{
+    const int64_t j = (i + o) % n;
+    const int64_t a = t[i], b = t[(i + 1) % n], c = t[j], e = t[(j + 1) % n];
+    return oracle_dist(xy, a, c) + oracle_dist(xy, b, e) - oracle_dist(xy, a, b) -
+           oracle_dist(xy, c, e);
+}
+
+/* best move of every position: off[i] = 0 when no move has g < 0 */
+void oracle_two_opt_best(const int32_t *xy, int64_t n, const int32_t *tour, int64_t window,
+                         int64_t *gain, int64_t *off)
+{
+    const int64_t W = two_opt_window(n, window);
+    for (int64_t i = 0; i < n; ++i) {
+        gain[i] = 0;
+        off[i] = 0;
+        for (int64_t o = 2; o <= W; ++o) {
+            const int64_t g = two_opt_gain(xy, n, tour, i, o);
+            if (g < gain[i]) {
+                gain[i] = g;
+                off[i] = o;
+            }
+        }
+    }
+}
+
+/* Runs rounds until none improves or max_rounds (> 0) rounds have     */
+/* applied moves.  Returns the rounds that applied moves; *moves the    */
+/* moves, *gain their summed gains, *converged 1 when the last round    */
+/* found no improving move.                                             */
+int64_t oracle_two_opt(const int32_t *xy, int64_t n, int32_t *tour, int64_t window,
+                       int64_t max_rounds, int64_t *moves, int64_t *gain, int *converged)
+{
+    *moves = 0;
+    *gain = 0;
+    *converged = 1;
+    const int64_t W = two_opt_window(n, window);
+    if (W < 2) return 0;
+    int64_t *g = malloc((size_t)n * sizeof *g);
+    int64_t *o = malloc((size_t)n * sizeof *o);
+    uint8_t *take = malloc((size_t)n);
+    int64_t *cand = malloc((size_t)n * sizeof *cand);
+    int64_t rounds = 0;
+    for (;;) {
+        oracle_two_opt_best(xy, n, tour, window, g, o);
+        int64_t nc = 0;   /* positions with an improving move */
+        for (int64_t i = 0; i < n; ++i)
+            if (o[i] != 0) cand[nc++] = i;
+        if (nc == 0) break;
+        if (max_rounds > 0 && rounds == max_rounds) {
+            *converged = 0;
+            break;
+        }
+        /* choose: no overlapping move is better by (g, position) */
+        for (int64_t i = 0; i < n; ++i) {
+            take[i] = o[i] != 0;
+            for (int64_t x = 0; x < nc && take[i]; ++x) {
+                const int64_t u = cand[x];
+                if (u == i) continue;
+                /* spans [i, i+o[i]+1] and [u, u+o[u]+1] overlap (cyclic)? */
+                const int64_t du = (u - i + n) % n;   /* u's distance ahead of i */
+                const int64_t di = (i - u + n) % n;   /* i's distance ahead of u */
+                const int overlap = du <= o[i] + 1 || di <= o[u] + 1;
+                if (overlap && (g[u] < g[i] || (g[u] == g[i] && u < i))) take[i] = 0;
+            }
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            if (!take[i]) continue;
+            for (int64_t q = 0; q < o[i] / 2; ++q) {
+                const int64_t p1 = (i + 1 + q) % n, p2 = (i + o[i] - q) % n;
+                const int32_t tmp = tour[p1];
+                tour[p1] = tour[p2];
+                tour[p2] = tmp;
+            }
+            *moves += 1;
+            *gain += g[i];
+        }
+        ++rounds;
+    }
+    free(g);
+    free(o);
+    free(take);
+    free(cand);
+    return rounds;
+}
+
+/* ------------------------------------------------------------------ */
 /* Pheromone update: evaporation (Eq. 2) then the deposit of every ant  */
 /* (Eq. 3-4), Delta tau = 1/C^k on the edges of ant k's tour, quantised  */
 /* to int64 fixed point q = floor(2^shift / L) and accumulated exactly. */
