@@ -14,7 +14,9 @@ Further objects report the batched colonies (4,096 instances, one
 persistent launch, autotuned), the learned heuristic (training on the GPU,
 kernel rates, and the equal-wall-clock comparison with plain eta) and
 PartialACO (rebuilding at most 1% of each ant's local best per iteration,
-run for the plain colony's wall time).
+run for the plain colony's wall time), Independent Roulette, and windowed
+2-opt (alone on constructed tours, and inside PartialACO with p = 0.001,
+W = 500).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                     [--no-batched] [--no-learned] [--no-partial]
@@ -261,7 +263,8 @@ def learned_block(xy_eval, cfg):
     }
 
 
-def partial_block(xy, cfg, budget_s, pheromone_kind="table", sampler=0):
+def partial_block(xy, cfg, budget_s, pheromone_kind="table", sampler=0, two_opt_p=0.0,
+                  window=500):
     """PartialACO (Section 3.1, Algorithm 1) on the evaluation workload with
     the paper's 1% cap at 200K cities and p = 1: iteration 0 builds full
     tours (the local bests); every later iteration each ant rebuilds at most
@@ -271,7 +274,9 @@ def partial_block(xy, cfg, budget_s, pheromone_kind="table", sampler=0):
     colony's run time) from set-up.  pheromone_kind="table": the n x k table with
     evaporation and the iteration's deposits; "local_best": recomputed each
     iteration from the ants' local bests (the paper's P-ACO variant, base
-    1/(n-1), delta 1/m).  sampler 1: Independent Roulette (Section 3)."""
+    1/(n-1), delta 1/m).  sampler 1: Independent Roulette (Section 3).
+    two_opt_p > 0: after each construction the tours drawn with that
+    probability get windowed 2-opt (Sections 4-5: p = 0.001, W = 500)."""
     import torch
 
     import paper_1709_03187_amd as aco
@@ -290,7 +295,21 @@ def partial_block(xy, cfg, budget_s, pheromone_kind="table", sampler=0):
         else:
             col.pheromone_from_local_best(base, delta)
 
+    opt = dict(calls=0, tours=0, moves=0, gain=0, seconds=0.0)
+
+    def two_opt(it):
+        if two_opt_p <= 0:
+            return
+        t = time.time()
+        st = col.two_opt(it, p=two_opt_p, window=window)
+        opt["seconds"] += time.time() - t
+        opt["calls"] += 1
+        opt["tours"] += st["selected"]
+        opt["moves"] += st["moves"]
+        opt["gain"] += st["gain"]
+
     col.construct_ex(0, sampler=sampler)
+    two_opt(0)
     col.update_local_best()
     col.track_best()
     pheromone()
@@ -306,6 +325,7 @@ def partial_block(xy, cfg, budget_s, pheromone_kind="table", sampler=0):
         e[0].record(stream)
         col.construct_ex(its, sampler=sampler, p_partial=1.0, max_modify=M, partial=True)
         e[1].record(stream)
+        two_opt(its)
         col.update_local_best()
         col.track_best()
         e[2].record(stream)
@@ -328,6 +348,40 @@ def partial_block(xy, cfg, budget_s, pheromone_kind="table", sampler=0):
            "best_len": int(col.best_len.item()), "L_nn": col.L_nn,
            "mean_local_best_first": lb_first,
            "mean_local_best_last": float(col.lbest_len.double().mean().item())}
+    if two_opt_p > 0:
+        res["two_opt"] = dict(p=two_opt_p, window=window, **opt)
+    del col
+    torch.cuda.empty_cache()
+    return res
+
+
+def two_opt_block(xy, cfg, tours=4, window=500):
+    """Windowed 2-opt (Sections 4-5) of `tours` constructed tours of the main
+    workload at once (every tour takes part): wall time of the call, rounds,
+    moves and the length reduction.  The first round evaluates every move:
+    n (W - 1) per tour."""
+    import torch
+
+    import paper_1709_03187_amd as aco
+    n = cfg["n"]
+    col = aco.Colony(xy=xy, k=cfg["k"], m=tours, alpha=cfg["alpha"], beta=cfg["beta"],
+                     rho=cfg["rho"], seed=cfg["seed"])
+    col.setup()
+    out = []
+    for it in range(2):
+        col.construct(it)
+        L0 = col.lengths.double().sum().item()
+        torch.cuda.synchronize()
+        t = time.time()
+        st = col.two_opt(it, p=1.0, window=window, batch=tours)
+        torch.cuda.synchronize()
+        out.append(dict(seconds=time.time() - t, **st,
+                        length_reduction=-st["gain"] / L0))
+    w = min(window, n // 2)
+    res = {"tours": tours, "window": window, "runs": out,
+           "first_round_move_evaluations": tours * n * (w - 1),
+           "mean_len_after": float(col.lengths.double().mean().item()),
+           "L_nn": col.L_nn}
     del col
     torch.cuda.empty_cache()
     return res
@@ -510,6 +564,11 @@ def main():
         out["partial_independent_local_best"] = partial_block(xy, cfg, gpu_time, "local_best", 1)
         log("[bench] Independent Roulette, full tours")
         out["independent_roulette"] = independent_block(xy, cfg)
+        log("[bench] windowed 2-opt of constructed tours")
+        out["two_opt"] = two_opt_block(xy, cfg)
+        log("[bench] PartialACO + Independent Roulette + local-best pheromone + 2-opt")
+        out["partial_independent_local_best_two_opt"] = partial_block(
+            xy, cfg, gpu_time, "local_best", 1, two_opt_p=0.001, window=500)
     if not args.no_cpu_baseline:
         threads = args.cpu_threads or max(1, min(16, os.cpu_count() or 1))
         log(f"[bench] cpu baseline with {threads} threads")

@@ -329,6 +329,59 @@ int aco_pheromone_local_best(int32_t n, int32_t k, const int32_t *nn, const int8
                              void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Windowed 2-opt local search.  Section 4 applies 2-opt to a constructed
+ * tour with a small probability (0.001); Section 5 limits it to pairs of
+ * tour edges at most W = 500 positions apart.
+ *
+ * Tour a takes part when word 3 of the Philox block at counter
+ * (0, a, iteration, 0) is below round(p 2^32) (words 0-2 are the start city
+ * and PartialACO's plan).  Move (i, o), 2 <= o <= W' = min(W, n/2), j = i + o
+ * (positions mod n), replaces the edges (t_i, t_i+1), (t_j, t_j+1) by
+ * (t_i, t_j), (t_i+1, t_j+1), reversing t_i+1 .. t_j; its gain is
+ *     g = d(t_i, t_j) + d(t_i+1, t_j+1) - d(t_i, t_i+1) - d(t_j, t_j+1).
+ * Rounds: every position takes its best move (smallest g < 0, ties to the
+ * smaller o); a move is applied when no move whose span (positions i..j+1)
+ * meets its own is better by (g, i).  The applied moves are disjoint, their
+ * gains add.  Rounds repeat until no move has g < 0 (the tour is 2-optimal
+ * for all pairs of edges within W positions) or max_rounds rounds have
+ * applied moves.
+ * ------------------------------------------------------------------------ */
+
+#define ACO_TWO_OPT_MAX_WINDOW 2048
+
+typedef struct aco_two_opt_stats {
+    int32_t selected;  /* tours that took part */
+    int32_t converged; /* 1 when every such tour ended 2-optimal within the window */
+    int64_t rounds;    /* rounds that applied moves (the largest over the tours) */
+    int64_t moves;     /* moves applied, summed over the tours */
+    int64_t gain;      /* their summed gains (<= 0): the change of the summed lengths */
+} aco_two_opt_stats_t;
+
+/* Workspace for m ants on n cities, handling up to `batch` tours at once. */
+size_t aco_two_opt_workspace_bytes(int32_t n, int32_t m, int32_t batch);
+
+/* Windowed 2-opt of the participating tours, in place.
+ *   xy       int32 [n][2] coordinates
+ *   tours    int32 [m][n] closed tours (permutations of 0..n-1), rewritten
+ *   lengths  int64 [m] their lengths on entry; the gain is added
+ *   slots    uint8 [m][n] or NULL: construction records; the positions whose
+ *            incoming edge changed are set to 255 (no record), which the
+ *            pheromone update then locates in the candidate lists
+ *   window   W in [1, ACO_TWO_OPT_MAX_WINDOW] (W' < 2, i.e. n < 4 or W = 1,
+ *            allows no move)
+ *   p        participation probability in [0, 1]
+ *   max_rounds  0: until no move improves; > 0: at most this many rounds
+ *   stats    host pointer or NULL
+ *   ws       aco_two_opt_workspace_bytes(n, m, batch) bytes, batch >= 1
+ * Synchronises with `stream` once per call plus once per 16 rounds (the host
+ * reads how many moves each round applied).
+ * Errors: INVALID_ARG (sizes, window, p, NULL pointers), WORKSPACE, HIP. */
+int aco_two_opt(const int32_t *xy, int32_t n, int32_t m, int32_t *tours, int64_t *lengths,
+                uint8_t *slots, int32_t window, double p, uint64_t seed, int64_t iteration,
+                int64_t max_rounds, int32_t batch, aco_two_opt_stats_t *stats, void *ws,
+                size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * Learned heuristic.  A small network scores every candidate edge from its
  * local geometry, and sigmoid(score) replaces eta = 1/d in the weights
  * tau^alpha * eta^beta of Eq. 1 (Section 2); the colony itself is unchanged.

@@ -39,7 +39,9 @@ EXPORTS = (
     "aco_edge_features", "aco_mlp_forward", "aco_mlp_backward_workspace_bytes",
     "aco_mlp_backward", "aco_mlp_adam", "aco_tour_edge_labels", "aco_construct_partial",
     "aco_update_local_best", "aco_pheromone_local_best", "aco_construct_ex",
+    "aco_two_opt_workspace_bytes", "aco_two_opt",
 )
+ACO_TWO_OPT_MAX_WINDOW = 2048
 ACO_SAMPLER_ROULETTE = 0
 ACO_SAMPLER_INDEPENDENT = 1
 ACO_MLP_PARAMS = 4801
@@ -64,6 +66,11 @@ class AcoParams(C.Structure):
 class AcoConstructOpts(C.Structure):
     _fields_ = [("sampler", C.c_int32), ("p_partial", C.c_double), ("max_modify", C.c_int32),
                 ("lbest", C.c_void_p)]
+
+
+class AcoTwoOptStats(C.Structure):
+    _fields_ = [("selected", C.c_int32), ("converged", C.c_int32), ("rounds", C.c_int64),
+                ("moves", C.c_int64), ("gain", C.c_int64)]
 
 
 class AcoBatchLayout(C.Structure):
@@ -120,6 +127,9 @@ def lib():
                                                    sz, p]),
             "aco_construct_ex": (C.c_int, [p, i32, i32, p, p, p, p, p, i32, i32, dbl, u64, i64,
                                            C.POINTER(AcoConstructOpts), p, p, p, p, p, sz, p]),
+            "aco_two_opt_workspace_bytes": (sz, [i32, i32, i32]),
+            "aco_two_opt": (C.c_int, [p, i32, i32, p, p, p, i32, dbl, u64, i64, i64, i32,
+                                      C.POINTER(AcoTwoOptStats), p, sz, p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -290,6 +300,24 @@ def aco_pheromone_local_best(n, k, nn, rev, m, lbest, lbest_len, tau_base, delta
         _ptr(ws, torch.uint8, "ws"), ws.numel(), _stream(stream)))
 
 
+def aco_two_opt_workspace_bytes(n, m, batch) -> int:
+    return int(lib().aco_two_opt_workspace_bytes(int(n), int(m), int(batch)))
+
+
+def aco_two_opt(xy, n, m, tours, lengths, slots, window, p, seed, iteration, max_rounds, batch, ws,
+                stream=None) -> dict:
+    """Windowed 2-opt of the participating tours (in place); returns the call's statistics."""
+    torch = _t()
+    st = AcoTwoOptStats()
+    _check(lib().aco_two_opt(
+        _ptr(xy, torch.int32, "xy"), n, m, _ptr(tours, torch.int32, "tours"),
+        _ptr(lengths, torch.int64, "lengths"), _ptr(slots, torch.uint8, "slots"), int(window),
+        float(p), int(seed), int(iteration), int(max_rounds), int(batch), C.byref(st),
+        _ptr(ws, torch.uint8, "ws"), ws.numel(), _stream(stream)))
+    return dict(selected=st.selected, converged=bool(st.converged), rounds=st.rounds,
+                moves=st.moves, gain=st.gain)
+
+
 # ------------------------------------------------------------ learned heuristic
 def aco_features_workspace_bytes() -> int:
     return int(lib().aco_features_workspace_bytes())
@@ -453,6 +481,16 @@ class Colony:
         aco_pheromone_local_best(self.n, self.k, self.nn, self.rev, self.m, self.lbest,
                                  self.lbest_len, tau_base, delta, self.deposit_shift, self.tau,
                                  self.uws, stream)
+
+    def two_opt(self, iteration, p=0.001, window=500, max_rounds=0, batch=8, stream=None):
+        """Windowed 2-opt of the tours that take part this iteration (in place; lengths and
+        construction records follow).  Returns the call's statistics."""
+        torch = _t()
+        need = aco_two_opt_workspace_bytes(self.n, self.m, batch)
+        if getattr(self, "tws", None) is None or self.tws.numel() < need:
+            self.tws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        return aco_two_opt(self.xy, self.n, self.m, self.tours, self.lengths, self.slots, window,
+                           p, self.seed, iteration, max_rounds, batch, self.tws, stream)
 
     def track_best(self, iter_best=None, stream=None):
         aco_track_best(self.n, self.m, self.tours, self.lengths, self.best_len, self.best_tour,

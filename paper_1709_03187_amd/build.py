@@ -14,7 +14,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libaco.so")
-SOURCES = ["candidates.hip", "construct.hip", "update.hip", "batch.hip", "mlp.hip", "capi.hip"]
+SOURCES = ["candidates.hip", "construct.hip", "update.hip", "batch.hip", "mlp.hip", "two_opt.hip",
+           "capi.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

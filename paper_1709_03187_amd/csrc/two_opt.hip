@@ -1,0 +1,369 @@
+// Windowed 2-opt local search (2-opt with a small probability, Section 4;
+// moves limited to edges within W tour positions, Section 5).
+//
+// Rounds of non-overlapping best moves, so that one round applies many moves
+// at once.  Per round and tour:
+//   k_two_opt_eval    one thread per position i evaluates its W' - 1 moves
+//                     from an LDS tile of the coordinates of positions
+//                     i0 .. i0 + 256 + W' + 1 and keeps the best as one int64
+//                     key g * 2^12 + o (g < 0), or kNone;
+//   k_two_opt_accept  a position's move is taken when no move whose span
+//                     meets its own is better by (g, position), read from an
+//                     LDS tile of keys i0 - W' - 1 .. i0 + 256 + W';
+//   k_two_opt_apply   one wave per taken move reverses t[i+1 .. i+o], marks
+//                     the changed construction records and the tiles whose
+//                     keys read a changed position.
+// Only tiles marked by the previous round are evaluated again: a key depends
+// on positions i .. i + W' + 1 alone, so the others are still exact.  All
+// distances are integers and all sums exact, so the result does not depend
+// on scheduling.
+#include <cmath>
+
+#include "common.hpp"
+#include "device.hpp"
+
+namespace aco {
+namespace {
+
+constexpr int kT = 256;                 // positions per workgroup
+constexpr int kOffBits = 12;            // offset field of a key (W <= 2048 < 4096)
+constexpr int64_t kOffMask = (1 << kOffBits) - 1;
+constexpr int64_t kNone = INT64_MAX;    // no improving move
+constexpr int kRoundsPerSync = 16;      // rounds launched between host reads
+constexpr int kApplyBlocks = 256;
+
+__device__ __forceinline__ int64_t d_int(int2 p, int2 q)
+{
+    return nint_sqrt(sq_dist(p.x, p.y, q.x, q.y));
+}
+
+// Participating ants, in increasing order: one workgroup, wave ballots.
+__global__ __launch_bounds__(kT) void k_two_opt_select(uint64_t seed, uint32_t iteration,
+                                                       int32_t m, uint64_t thr, int32_t *sel,
+                                                       int32_t *count, int64_t *gain_sum)
+{
+    __shared__ int32_t wsum[kT / kWave];
+    __shared__ int32_t base;
+    const int lane = lane_id(), w = threadIdx.x / kWave;
+    if (threadIdx.x == 0) {
+        base = 0;
+        *gain_sum = 0;
+    }
+    __syncthreads();
+    for (int32_t a0 = 0; a0 < m; a0 += kT) {
+        const int32_t a = a0 + (int32_t)threadIdx.x;
+        bool take = false;
+        if (a < m) {
+            const uint4 b = philox_block(0u, (uint32_t)a, iteration, 0u, (uint32_t)seed,
+                                         (uint32_t)(seed >> 32));
+            take = (uint64_t)b.w < thr;
+        }
+        const uint64_t bal = __builtin_amdgcn_ballot_w64(take);
+        if (lane == 0) wsum[w] = __popcll(bal);
+        __syncthreads();
+        int32_t off = base;
+        for (int q = 0; q < w; ++q) off += wsum[q];
+        if (take) sel[off + __popcll(bal & ((1ull << lane) - 1ull))] = a;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int q = 0; q < kT / kWave; ++q) base += wsum[q];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *count = base;
+}
+
+// Dirty flags: buffer 0 all set (round 0 evaluates every tile), buffer 1 clear.
+__global__ void k_two_opt_init(uint32_t *dirty, int32_t tiles, int32_t batch, int32_t S)
+{
+    const int64_t per = (int64_t)S * tiles;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < per;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        dirty[q] = 1u;
+        dirty[(int64_t)batch * tiles + q] = 0u;
+    }
+}
+
+__global__ void k_two_opt_zero(int32_t *p, int32_t count)
+{
+    for (int32_t q = threadIdx.x; q < count; q += blockDim.x) p[q] = 0;
+}
+
+// Best move of every position of the dirty tiles.  Grid (tiles, S).
+__global__ __launch_bounds__(kT) void k_two_opt_eval(const int32_t *__restrict__ xy,
+                                                     const int32_t *__restrict__ tours,
+                                                     const int32_t *__restrict__ ants, int32_t n,
+                                                     int32_t W, int32_t tiles,
+                                                     uint32_t *__restrict__ dirty_cur,
+                                                     int64_t *__restrict__ keys,
+                                                     int32_t *__restrict__ list_count)
+{
+    extern __shared__ int2 P[];   // coordinates of positions i0 .. i0 + kT + W + 1
+    __shared__ uint32_t go;
+    const int32_t s = blockIdx.y, tile = blockIdx.x;
+    if (threadIdx.x == 0) {
+        if (tile == 0) list_count[s] = 0;   // the previous round's list is consumed
+        uint32_t *flag = dirty_cur + (int64_t)s * tiles + tile;
+        go = *flag;
+        if (go) *flag = 0u;
+    }
+    __syncthreads();
+    if (!go) return;
+    const int32_t np = kT + W + 2;
+    int32_t *L = (int32_t *)(P + np);     // L[q] = d(P[q], P[q + 1])
+    const int32_t *tour = tours + (int64_t)ants[s] * n;
+    const int32_t i0 = tile * kT;
+    for (int32_t q = threadIdx.x; q < np; q += kT) {
+        const int32_t c = tour[((int64_t)i0 + q) % n];
+        const int64_t cc = (uint32_t)c < (uint32_t)n ? c : 0;   // a tour is a permutation
+        P[q] = make_int2(xy[2 * cc], xy[2 * cc + 1]);
+    }
+    __syncthreads();
+    for (int32_t q = threadIdx.x; q < np - 1; q += kT) L[q] = (int32_t)d_int(P[q], P[q + 1]);
+    __syncthreads();
+    const int32_t t = threadIdx.x, i = i0 + t;
+    if (i >= n) return;
+    const int2 a = P[t], b = P[t + 1];
+    const int64_t dab = L[t];
+    int64_t best = kNone;
+    for (int32_t o = 2; o <= W; ++o) {
+        const int64_t g = d_int(a, P[t + o]) + d_int(b, P[t + o + 1]) - dab - L[t + o];
+        const int64_t key = g * (1 << kOffBits) + o;
+        best = (g < 0 && key < best) ? key : best;
+    }
+    keys[(int64_t)s * n + i] = best;
+}
+
+// A position's move is taken when no overlapping move is better by (g, position).
+// Grid (tiles, S).
+__global__ __launch_bounds__(kT) void k_two_opt_accept(const int64_t *__restrict__ keys,
+                                                       int32_t n, int32_t W,
+                                                       int32_t *__restrict__ list,
+                                                       int32_t list_cap,
+                                                       int32_t *__restrict__ list_count,
+                                                       int32_t *__restrict__ round_moves)
+{
+    extern __shared__ int64_t K[];   // keys of positions i0 - W - 1 .. i0 + kT + W
+    const int32_t s = blockIdx.y, i0 = blockIdx.x * kT, t = threadIdx.x, i = i0 + t;
+    const int64_t *ks = keys + (int64_t)s * n;
+    const int64_t mine = i < n ? ks[i] : kNone;
+    if (!__syncthreads_or(mine != kNone)) return;
+    const int32_t nk = kT + 2 * W + 2;
+    for (int32_t q = t; q < nk; q += kT) {
+        int64_t pos = ((int64_t)i0 - W - 1 + q) % n;
+        pos += pos < 0 ? n : 0;
+        K[q] = ks[pos];
+    }
+    __syncthreads();
+    if (mine == kNone) return;
+    const int64_t g = mine >> kOffBits;
+    const int32_t o = (int32_t)(mine & kOffMask);
+    bool take = true;
+    // u = i + d: for d > 0 u lies in i's span (i .. i + o + 1); for d < 0 i
+    // lies in u's span when its offset reaches: o_u + 1 >= -d.  W + 1 < n, so
+    // one wrap correction suffices.
+    for (int32_t d = -(W + 1); d <= o + 1 && take; ++d) {
+        if (d == 0) continue;
+        const int64_t ku = K[t + W + 1 + d];
+        if (ku == kNone) continue;
+        if (d < 0 && (int32_t)(ku & kOffMask) + 1 < -d) continue;
+        const int64_t gu = ku >> kOffBits;
+        int32_t u = i + d;
+        u += u < 0 ? n : 0;
+        u -= u >= n ? n : 0;
+        if (gu < g || (gu == g && u < i)) take = false;
+    }
+    if (take) {
+        const int32_t e = atomicAdd(&list_count[s], 1);
+        if (e < list_cap) list[(int64_t)s * list_cap + e] = i;
+        atomicAdd(round_moves, 1);
+    }
+}
+
+// One wave per taken move.  Grid (kApplyBlocks, S).
+__global__ __launch_bounds__(kT) void k_two_opt_apply(
+    const int64_t *__restrict__ keys, const int32_t *__restrict__ list, int32_t list_cap,
+    const int32_t *__restrict__ list_count, const int32_t *__restrict__ ants, int32_t n, int32_t W,
+    int32_t tiles, int32_t *__restrict__ tours, int64_t *__restrict__ lengths,
+    uint8_t *__restrict__ slots, uint32_t *__restrict__ dirty_next, int64_t *__restrict__ gain_sum)
+{
+    const int32_t s = blockIdx.y;
+    const int lane = lane_id();
+    const int32_t wave = (int32_t)((blockIdx.x * kT + threadIdx.x) / kWave);
+    const int32_t nw = (int32_t)(gridDim.x * (kT / kWave));
+    const int32_t cnt = min(list_count[s], list_cap);
+    const int32_t ant = ants[s];
+    int32_t *tour = tours + (int64_t)ant * n;
+    for (int32_t e = wave; e < cnt; e += nw) {
+        const int32_t i = list[(int64_t)s * list_cap + e];
+        const int64_t key = keys[(int64_t)s * n + i];
+        const int32_t o = (int32_t)(key & kOffMask);
+        const int64_t g = key >> kOffBits;
+        // reverse positions i + 1 .. i + o (each lane swaps its own pairs)
+        for (int32_t q = lane; q < o / 2; q += kWave) {
+            int32_t p1 = i + 1 + q, p2 = i + o - q;
+            p1 -= p1 >= n ? n : 0;
+            p2 -= p2 >= n ? n : 0;
+            const int32_t v1 = tour[p1], v2 = tour[p2];
+            tour[p1] = v2;
+            tour[p2] = v1;
+        }
+        // incoming edges of positions i + 1 .. i + o + 1 changed
+        if (slots)
+            for (int32_t q = lane; q <= o; q += kWave) {
+                int32_t p = i + 1 + q;
+                p -= p >= n ? n : 0;
+                slots[(int64_t)ant * n + p] = (uint8_t)255;
+            }
+        // keys of positions i - W .. i + o read a changed position: mark their
+        // tiles.  The cyclic range is one or two linear pieces; each covers at
+        // most count / kT + 2 tiles, so 64 lanes suffice (count <= 2W + 1).
+        const int32_t first = i - W < 0 ? i - W + n : i - W;
+        const int32_t count = W + o + 1;
+        const int32_t last = first + count - 1;   // < 2n
+        int32_t a1 = first, b1 = last < n ? last : n - 1, b2 = last - n;
+        if (count >= n) {
+            a1 = 0;
+            b1 = n - 1;
+            b2 = -1;
+        }
+        const int32_t t1 = a1 / kT, nt1 = b1 / kT - t1 + 1;
+        const int32_t nt2 = b2 >= 0 ? b2 / kT + 1 : 0;
+        if (lane < nt1)
+            dirty_next[(int64_t)s * tiles + t1 + lane] = 1u;
+        else if (lane < nt1 + nt2)
+            dirty_next[(int64_t)s * tiles + (lane - nt1)] = 1u;
+        if (lane == 0) {
+            atomicAdd((unsigned long long *)&lengths[ant], (unsigned long long)g);
+            atomicAdd((unsigned long long *)gain_sum, (unsigned long long)g);
+        }
+    }
+}
+
+struct TwoOptLayout {
+    int32_t tiles, list_cap;
+    size_t sel, ctl, keys, list, dirty, total;
+    TwoOptLayout(int32_t n, int32_t m, int32_t batch)
+    {
+        auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+        tiles = (n + kT - 1) / kT;
+        list_cap = n / 4 + 1;   // taken spans are disjoint, each >= 4 positions
+        sel = 0;
+        ctl = up((size_t)m * 4);
+        // gain_sum int64, sel_count int32, round_moves int32[16], list_count int32[batch]
+        keys = ctl + up(8 + 4 + 4 * kRoundsPerSync + 4 * (size_t)batch);
+        list = keys + up((size_t)batch * n * 8);
+        dirty = list + up((size_t)batch * list_cap * 4);
+        total = dirty + up((size_t)2 * batch * tiles * 4);
+    }
+};
+
+}  // namespace
+}  // namespace aco
+
+using namespace aco;
+
+extern "C" size_t aco_two_opt_workspace_bytes(int32_t n, int32_t m, int32_t batch)
+{
+    if (n < 1 || m < 1 || batch < 1) return 0;
+    return TwoOptLayout(n, m, batch).total;
+}
+
+extern "C" int aco_two_opt(const int32_t *xy, int32_t n, int32_t m, int32_t *tours,
+                           int64_t *lengths, uint8_t *slots, int32_t window, double p,
+                           uint64_t seed, int64_t iteration, int64_t max_rounds, int32_t batch,
+                           aco_two_opt_stats_t *stats, void *ws, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    ACO_REQUIRE(n >= 3 && n <= (1 << 27), "n = %d out of range [3, 2^27]", n);
+    ACO_REQUIRE(m >= 1, "m = %d must be >= 1", m);
+    ACO_REQUIRE(window >= 1 && window <= ACO_TWO_OPT_MAX_WINDOW, "window = %d out of [1, %d]",
+                window, ACO_TWO_OPT_MAX_WINDOW);
+    ACO_REQUIRE(std::isfinite(p) && p >= 0.0 && p <= 1.0, "p = %g out of [0, 1]", p);
+    ACO_REQUIRE(iteration >= 0 && iteration <= (int64_t)UINT32_MAX, "iteration out of range");
+    ACO_REQUIRE(max_rounds >= 0, "max_rounds must be >= 0");
+    ACO_REQUIRE(batch >= 1, "batch = %d must be >= 1", batch);
+    ACO_REQUIRE(xy && tours && lengths && ws, "NULL array argument");
+    const TwoOptLayout lay(n, m, batch);
+    if (ws_bytes < lay.total)
+        return fail(ACO_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, lay.total);
+    hipStream_t st = as_stream(stream);
+    char *base = (char *)ws;
+    int32_t *sel = (int32_t *)(base + lay.sel);
+    int64_t *gain_sum = (int64_t *)(base + lay.ctl);
+    int32_t *sel_count = (int32_t *)(base + lay.ctl + 8);
+    int32_t *round_moves = sel_count + 1;
+    int32_t *list_count = round_moves + kRoundsPerSync;
+    int64_t *keys = (int64_t *)(base + lay.keys);
+    int32_t *list = (int32_t *)(base + lay.list);
+    uint32_t *dirty = (uint32_t *)(base + lay.dirty);
+
+    const uint64_t thr = (uint64_t)std::nearbyint(std::ldexp(p, 32));
+    k_two_opt_select<<<1, kT, 0, st>>>(seed, (uint32_t)iteration, m, thr, sel, sel_count,
+                                       gain_sum);
+    ACO_LAUNCH_CHECK("k_two_opt_select");
+    int32_t selected = 0;
+    ACO_HIP_CHECK(hipMemcpyAsync(&selected, sel_count, 4, hipMemcpyDeviceToHost, st));
+    ACO_HIP_CHECK(hipStreamSynchronize(st));
+
+    const int32_t W = window < n / 2 ? window : n / 2;   // each edge pair from its nearer side
+    aco_two_opt_stats_t out{selected, 1, 0, 0, 0};
+    if (selected > 0 && W >= 2) {
+        const size_t lds_eval = (size_t)(kT + W + 2) * sizeof(int2) + (size_t)(kT + W + 1) * 4;
+        const size_t lds_acc = (size_t)(kT + 2 * W + 2) * sizeof(int64_t);
+        for (int32_t c0 = 0; c0 < selected; c0 += batch) {
+            const int32_t S = selected - c0 < batch ? selected - c0 : batch;
+            const int32_t *ants = sel + c0;
+            k_two_opt_init<<<blocks_for((int64_t)S * lay.tiles, 256), 256, 0, st>>>(
+                dirty, lay.tiles, batch, S);
+            ACO_LAUNCH_CHECK("k_two_opt_init");
+            int64_t r = 0, improving = 0;
+            bool done = false, converged = true;
+            while (!done) {
+                int32_t nb = kRoundsPerSync;
+                if (max_rounds > 0 && max_rounds - r + 1 < nb) nb = (int32_t)(max_rounds - r + 1);
+                k_two_opt_zero<<<1, 64, 0, st>>>(round_moves, nb);
+                ACO_LAUNCH_CHECK("k_two_opt_zero");
+                for (int32_t b = 0; b < nb; ++b) {
+                    const int64_t rr = r + b;
+                    uint32_t *cur = dirty + (size_t)(rr & 1) * batch * lay.tiles;
+                    uint32_t *nxt = dirty + (size_t)((rr + 1) & 1) * batch * lay.tiles;
+                    k_two_opt_eval<<<dim3(lay.tiles, S), kT, lds_eval, st>>>(
+                        xy, tours, ants, n, W, lay.tiles, cur, keys, list_count);
+                    ACO_LAUNCH_CHECK("k_two_opt_eval");
+                    k_two_opt_accept<<<dim3(lay.tiles, S), kT, lds_acc, st>>>(
+                        keys, n, W, list, lay.list_cap, list_count, round_moves + b);
+                    ACO_LAUNCH_CHECK("k_two_opt_accept");
+                    // after max_rounds rounds, one more look only decides convergence
+                    if (max_rounds == 0 || rr < max_rounds) {
+                        k_two_opt_apply<<<dim3(kApplyBlocks, S), kT, 0, st>>>(
+                            keys, list, lay.list_cap, list_count, ants, n, W, lay.tiles, tours,
+                            lengths, slots, nxt, gain_sum);
+                        ACO_LAUNCH_CHECK("k_two_opt_apply");
+                    }
+                }
+                int32_t mv[kRoundsPerSync];
+                ACO_HIP_CHECK(
+                    hipMemcpyAsync(mv, round_moves, 4 * (size_t)nb, hipMemcpyDeviceToHost, st));
+                ACO_HIP_CHECK(hipStreamSynchronize(st));
+                for (int32_t b = 0; b < nb && !done; ++b) {
+                    if (mv[b] == 0) {
+                        done = true;
+                    } else if (max_rounds > 0 && r + b == max_rounds) {
+                        converged = false;
+                        done = true;
+                    } else {
+                        ++improving;
+                        out.moves += mv[b];
+                    }
+                }
+                r += nb;
+            }
+            out.rounds = improving > out.rounds ? improving : out.rounds;
+            out.converged &= converged ? 1 : 0;
+        }
+        ACO_HIP_CHECK(hipMemcpyAsync(&out.gain, gain_sum, 8, hipMemcpyDeviceToHost, st));
+        ACO_HIP_CHECK(hipStreamSynchronize(st));
+    }
+    if (stats) *stats = out;
+    return ACO_OK;
+}
