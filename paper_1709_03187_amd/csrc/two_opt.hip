@@ -37,6 +37,48 @@ __device__ __forceinline__ int64_t d_int(int2 p, int2 q)
     return nint_sqrt(sq_dist(p.x, p.y, q.x, q.y));
 }
 
+// nint(sqrt(dx^2 + dy^2)) for |dx|, |dy| < 2^21, exactly, without 64-bit
+// integer products: s < 2^43 is exact in FP64; the FP32 root of fl32(s) is
+// within 2^-22.7 relative, i.e. < 0.45 absolute, of sqrt(s) (below 2^21.5), so
+// k = rint(root) is nint(sqrt(s)) or one off; sqrt(s) >= k + 1/2 iff
+// s > k^2 + k and sqrt(s) < k - 1/2 iff s <= k^2 - k (k >= 1), both exact in
+// FP64 (sqrt(s) is never a half-integer).
+__device__ __forceinline__ double d_small(int2 p, int2 q)
+{
+    const double dx = (double)(p.x - q.x), dy = (double)(p.y - q.y);
+    const double s = __builtin_fma(dx, dx, dy * dy);
+    const double k = (double)__builtin_rintf(__builtin_amdgcn_sqrtf((float)s));   // v_sqrt_f32, 1 ulp
+    const double hi = __builtin_fma(k, k, k), lo = __builtin_fma(k, k, -k);
+    return k + (s > hi ? 1.0 : 0.0) - ((k > 0.0 && s <= lo) ? 1.0 : 0.0);
+}
+
+// Best key of position t of the tile (the distance type decides the path).
+template <bool kSmall>
+__device__ __forceinline__ int64_t best_move(const int2 *P, const int32_t *L, int32_t t,
+                                             int32_t W)
+{
+    const int2 a = P[t], b = P[t + 1];
+    int64_t best = kNone;
+    if constexpr (kSmall) {
+        // all terms are integers below 2^33: FP64 sums are exact
+        const double dab = (double)L[t];
+        for (int32_t o = 2; o <= W; ++o) {
+            const double g = d_small(a, P[t + o]) + d_small(b, P[t + o + 1]) - dab -
+                             (double)L[t + o];
+            const int64_t key = (int64_t)g * (1 << kOffBits) + o;
+            best = (g < 0.0 && key < best) ? key : best;
+        }
+    } else {
+        const int64_t dab = L[t];
+        for (int32_t o = 2; o <= W; ++o) {
+            const int64_t g = d_int(a, P[t + o]) + d_int(b, P[t + o + 1]) - dab - L[t + o];
+            const int64_t key = g * (1 << kOffBits) + o;
+            best = (g < 0 && key < best) ? key : best;
+        }
+    }
+    return best;
+}
+
 // Participating ants, in increasing order: one workgroup, wave ballots.
 __global__ __launch_bounds__(kT) void k_two_opt_select(uint64_t seed, uint32_t iteration,
                                                        int32_t m, uint64_t thr, int32_t *sel,
@@ -99,12 +141,15 @@ __global__ __launch_bounds__(kT) void k_two_opt_eval(const int32_t *__restrict__
 {
     extern __shared__ int2 P[];   // coordinates of positions i0 .. i0 + kT + W + 1
     __shared__ uint32_t go;
+    __shared__ int32_t box[4];    // min x, max x, min y, max y of the tile
     const int32_t s = blockIdx.y, tile = blockIdx.x;
     if (threadIdx.x == 0) {
         if (tile == 0) list_count[s] = 0;   // the previous round's list is consumed
         uint32_t *flag = dirty_cur + (int64_t)s * tiles + tile;
         go = *flag;
         if (go) *flag = 0u;
+        box[0] = box[2] = INT32_MAX;
+        box[1] = box[3] = INT32_MIN;
     }
     __syncthreads();
     if (!go) return;
@@ -112,25 +157,29 @@ __global__ __launch_bounds__(kT) void k_two_opt_eval(const int32_t *__restrict__
     int32_t *L = (int32_t *)(P + np);     // L[q] = d(P[q], P[q + 1])
     const int32_t *tour = tours + (int64_t)ants[s] * n;
     const int32_t i0 = tile * kT;
+    int32_t x0 = INT32_MAX, x1 = INT32_MIN, y0 = INT32_MAX, y1 = INT32_MIN;
     for (int32_t q = threadIdx.x; q < np; q += kT) {
         const int32_t c = tour[((int64_t)i0 + q) % n];
         const int64_t cc = (uint32_t)c < (uint32_t)n ? c : 0;   // a tour is a permutation
-        P[q] = make_int2(xy[2 * cc], xy[2 * cc + 1]);
+        const int2 pt = make_int2(xy[2 * cc], xy[2 * cc + 1]);
+        P[q] = pt;
+        x0 = min(x0, pt.x);
+        x1 = max(x1, pt.x);
+        y0 = min(y0, pt.y);
+        y1 = max(y1, pt.y);
     }
+    atomicMin(&box[0], x0);
+    atomicMax(&box[1], x1);
+    atomicMin(&box[2], y0);
+    atomicMax(&box[3], y1);
     __syncthreads();
     for (int32_t q = threadIdx.x; q < np - 1; q += kT) L[q] = (int32_t)d_int(P[q], P[q + 1]);
     __syncthreads();
     const int32_t t = threadIdx.x, i = i0 + t;
     if (i >= n) return;
-    const int2 a = P[t], b = P[t + 1];
-    const int64_t dab = L[t];
-    int64_t best = kNone;
-    for (int32_t o = 2; o <= W; ++o) {
-        const int64_t g = d_int(a, P[t + o]) + d_int(b, P[t + o + 1]) - dab - L[t + o];
-        const int64_t key = g * (1 << kOffBits) + o;
-        best = (g < 0 && key < best) ? key : best;
-    }
-    keys[(int64_t)s * n + i] = best;
+    // coordinates span less than 2^21 in both axes: every difference is small
+    const bool small = (int64_t)box[1] - box[0] < (1 << 21) && (int64_t)box[3] - box[2] < (1 << 21);
+    keys[(int64_t)s * n + i] = small ? best_move<true>(P, L, t, W) : best_move<false>(P, L, t, W);
 }
 
 // A position's move is taken when no overlapping move is better by (g, position).

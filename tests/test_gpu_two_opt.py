@@ -79,6 +79,21 @@ def test_random_tours_match_the_oracle(n, window):
     _compare(xy, tours, window, "random")
 
 
+def test_wide_coordinates_take_the_integer_path():
+    """Coordinates spanning more than 2^21 (up to the library's 2^29 limit) use the
+    64-bit integer distance; a clustered instance mixes tiles of both kinds."""
+    xy = instances.uniform_coords(700, 77, hi=2**29 - 1)
+    rng = np.random.default_rng(77)
+    tours = np.stack([rng.permutation(700) for _ in range(2)]).astype(np.int32)
+    _compare(xy, tours, 40, "wide")
+    near = instances.uniform_coords(600, 78, hi=1_000_000)
+    far = instances.uniform_coords(600, 79, hi=1_000_000) + np.int32(2**28)
+    xy = np.concatenate([near, far]).astype(np.int32)
+    tours = np.stack([np.concatenate([rng.permutation(600), 600 + rng.permutation(600)])
+                      for _ in range(2)]).astype(np.int32)
+    _compare(xy, tours, 100, "mixed")
+
+
 @pytest.mark.parametrize("n", [3, 4, 5, 6, 7, 9, 16, 257, 515])
 def test_small_and_ragged_sizes(n):
     """n below 4 allows no move; W' = min(W, n/2) wraps the windows round small tours;
