@@ -40,43 +40,62 @@ __device__ __forceinline__ int64_t d_int(int2 p, int2 q)
 // nint(sqrt(dx^2 + dy^2)) for |dx|, |dy| < 2^21, exactly, without 64-bit
 // integer products: s < 2^43 is exact in FP64; the FP32 root of fl32(s) is
 // within 2^-22.7 relative, i.e. < 0.45 absolute, of sqrt(s) (below 2^21.5), so
-// k = rint(root) is nint(sqrt(s)) or one off; sqrt(s) >= k + 1/2 iff
-// s > k^2 + k and sqrt(s) < k - 1/2 iff s <= k^2 - k (k >= 1), both exact in
-// FP64 (sqrt(s) is never a half-integer).
-__device__ __forceinline__ double d_small(int2 p, int2 q)
+// k = rint(root) is nint(sqrt(s)) or one off.  With t = s - k^2 (exact):
+// sqrt(s) >= k + 1/2 iff t > k, and sqrt(s) < k - 1/2 iff t <= -k for k >= 1
+// (sqrt(s) is never a half-integer; k = 0 only for s = 0).
+__device__ __forceinline__ int32_t d_small(int2 p, int2 q)
 {
     const double dx = (double)(p.x - q.x), dy = (double)(p.y - q.y);
     const double s = __builtin_fma(dx, dx, dy * dy);
-    const double k = (double)__builtin_rintf(__builtin_amdgcn_sqrtf((float)s));   // v_sqrt_f32, 1 ulp
-    const double hi = __builtin_fma(k, k, k), lo = __builtin_fma(k, k, -k);
-    return k + (s > hi ? 1.0 : 0.0) - ((k > 0.0 && s <= lo) ? 1.0 : 0.0);
+    const float kf = __builtin_rintf(__builtin_amdgcn_sqrtf((float)s));   // v_sqrt_f32, 1 ulp
+    const double k = (double)kf;
+    const double t = __builtin_fma(-k, k, s);
+    return (int32_t)kf + (t > k ? 1 : 0) - ((kf > 0.0f && t <= -k) ? 1 : 0);
 }
 
-// Best key of position t of the tile (the distance type decides the path).
+// Evaluation tiles: each wave covers 63 positions; its lane l computes
+// D_o(q) = d(t_q, t_q+o) for q = its position, and the gain of move (q, o)
+// takes D_o(q + 1) from lane l + 1 (so lane 63 only supplies that distance):
+//   g(q, o) = D_o(q) + D_o(q + 1) - L[q] - L[q + o].
+constexpr int kPosPerWave = kWave - 1;
+constexpr int kTE = (kT / kWave) * kPosPerWave;   // 252 positions per evaluation tile
+
+// The value of lane l + 1 (DPP wave shift by one lane; lane 63 receives 0).
+__device__ __forceinline__ int32_t from_next_lane(int32_t v)
+{
+    return __builtin_amdgcn_mov_dpp(v, 0x130 /* wave_shl:1 */, 0xf, 0xf, true);
+}
+
+// Best key of tile position q (lanes 63 return garbage, unused).
 template <bool kSmall>
-__device__ __forceinline__ int64_t best_move(const int2 *P, const int32_t *L, int32_t t,
+__device__ __forceinline__ int64_t best_move(const int2 *P, const int32_t *L, int32_t q,
                                              int32_t W)
 {
-    const int2 a = P[t], b = P[t + 1];
-    int64_t best = kNone;
+    const int2 a = P[q];
+    const int32_t lq = L[q];
     if constexpr (kSmall) {
-        // all terms are integers below 2^33: FP64 sums are exact
-        const double dab = (double)L[t];
+        // distances below 2^21.5: gains fit in int32
+        int32_t bg = 0, bo = 0;
         for (int32_t o = 2; o <= W; ++o) {
-            const double g = d_small(a, P[t + o]) + d_small(b, P[t + o + 1]) - dab -
-                             (double)L[t + o];
-            const int64_t key = (int64_t)g * (1 << kOffBits) + o;
-            best = (g < 0.0 && key < best) ? key : best;
+            const int32_t dq = d_small(a, P[q + o]);
+            const int32_t dq1 = from_next_lane(dq);
+            const int32_t g = dq + dq1 - lq - L[q + o];
+            bo = g < bg ? o : bo;          // strict: the smaller offset keeps a tie
+            bg = g < bg ? g : bg;
         }
+        return bg < 0 ? (int64_t)bg * (1 << kOffBits) + bo : kNone;
     } else {
-        const int64_t dab = L[t];
+        int64_t bg = 0;
+        int32_t bo = 0;
         for (int32_t o = 2; o <= W; ++o) {
-            const int64_t g = d_int(a, P[t + o]) + d_int(b, P[t + o + 1]) - dab - L[t + o];
-            const int64_t key = g * (1 << kOffBits) + o;
-            best = (g < 0 && key < best) ? key : best;
+            const int32_t dq = (int32_t)d_int(a, P[q + o]);   // < 2^31 for |coords| < 2^29
+            const int32_t dq1 = from_next_lane(dq);
+            const int64_t g = (int64_t)dq + dq1 - lq - L[q + o];
+            bo = g < bg ? o : bo;
+            bg = g < bg ? g : bg;
         }
+        return bg < 0 ? bg * (1 << kOffBits) + bo : kNone;
     }
-    return best;
 }
 
 // Participating ants, in increasing order: one workgroup, wave ballots.
@@ -139,7 +158,7 @@ __global__ __launch_bounds__(kT) void k_two_opt_eval(const int32_t *__restrict__
                                                      int64_t *__restrict__ keys,
                                                      int32_t *__restrict__ list_count)
 {
-    extern __shared__ int2 P[];   // coordinates of positions i0 .. i0 + kT + W + 1
+    extern __shared__ int2 P[];   // coordinates of positions i0 .. i0 + kTE + W + 1
     __shared__ uint32_t go;
     __shared__ int32_t box[4];    // min x, max x, min y, max y of the tile
     const int32_t s = blockIdx.y, tile = blockIdx.x;
@@ -153,10 +172,10 @@ __global__ __launch_bounds__(kT) void k_two_opt_eval(const int32_t *__restrict__
     }
     __syncthreads();
     if (!go) return;
-    const int32_t np = kT + W + 2;
+    const int32_t np = kTE + W + 2;
     int32_t *L = (int32_t *)(P + np);     // L[q] = d(P[q], P[q + 1])
     const int32_t *tour = tours + (int64_t)ants[s] * n;
-    const int32_t i0 = tile * kT;
+    const int32_t i0 = tile * kTE;
     int32_t x0 = INT32_MAX, x1 = INT32_MIN, y0 = INT32_MAX, y1 = INT32_MIN;
     for (int32_t q = threadIdx.x; q < np; q += kT) {
         const int32_t c = tour[((int64_t)i0 + q) % n];
@@ -175,15 +194,21 @@ __global__ __launch_bounds__(kT) void k_two_opt_eval(const int32_t *__restrict__
     __syncthreads();
     for (int32_t q = threadIdx.x; q < np - 1; q += kT) L[q] = (int32_t)d_int(P[q], P[q + 1]);
     __syncthreads();
-    const int32_t t = threadIdx.x, i = i0 + t;
-    if (i >= n) return;
-    // coordinates span less than 2^21 in both axes: every difference is small
+    // whole waves run the loop (lane l + 1 feeds lane l); coordinates spanning
+    // less than 2^21 in both axes make every difference small
+    const int lane = lane_id();
+    const int32_t q = (int32_t)(threadIdx.x / kWave) * kPosPerWave + lane, i = i0 + q;
     const bool small = (int64_t)box[1] - box[0] < (1 << 21) && (int64_t)box[3] - box[2] < (1 << 21);
-    keys[(int64_t)s * n + i] = small ? best_move<true>(P, L, t, W) : best_move<false>(P, L, t, W);
+    const int64_t key = small ? best_move<true>(P, L, q, W) : best_move<false>(P, L, q, W);
+    if (lane < kPosPerWave && i < n) keys[(int64_t)s * n + i] = key;
 }
 
 // A position's move is taken when no overlapping move is better by (g, position).
-// Grid (tiles, S).
+// Grid (ceil(n / kT), S).  Each wave takes the candidates among its 64
+// positions one at a time and checks the moves that can overlap with all
+// lanes, nearest first, 64 at a time, stopping at the first better one: moves
+// starting inside the span (d = 1 .. o + 1 ahead; they always overlap), then
+// moves starting d = 1 .. W + 1 before it (they overlap when o_u + 1 >= d).
 __global__ __launch_bounds__(kT) void k_two_opt_accept(const int64_t *__restrict__ keys,
                                                        int32_t n, int32_t W,
                                                        int32_t *__restrict__ list,
@@ -203,28 +228,40 @@ __global__ __launch_bounds__(kT) void k_two_opt_accept(const int64_t *__restrict
         K[q] = ks[pos];
     }
     __syncthreads();
-    if (mine == kNone) return;
-    const int64_t g = mine >> kOffBits;
-    const int32_t o = (int32_t)(mine & kOffMask);
-    bool take = true;
-    // u = i + d: for d > 0 u lies in i's span (i .. i + o + 1); for d < 0 i
-    // lies in u's span when its offset reaches: o_u + 1 >= -d.  W + 1 < n, so
-    // one wrap correction suffices.
-    for (int32_t d = -(W + 1); d <= o + 1 && take; ++d) {
-        if (d == 0) continue;
-        const int64_t ku = K[t + W + 1 + d];
-        if (ku == kNone) continue;
-        if (d < 0 && (int32_t)(ku & kOffMask) + 1 < -d) continue;
-        const int64_t gu = ku >> kOffBits;
-        int32_t u = i + d;
-        u += u < 0 ? n : 0;
-        u -= u >= n ? n : 0;
-        if (gu < g || (gu == g && u < i)) take = false;
-    }
-    if (take) {
-        const int32_t e = atomicAdd(&list_count[s], 1);
-        if (e < list_cap) list[(int64_t)s * list_cap + e] = i;
-        atomicAdd(round_moves, 1);
+    const int lane = lane_id();
+    const int32_t w0 = (int32_t)(t / kWave) * kWave;   // first tile position of this wave
+    uint64_t cand = __builtin_amdgcn_ballot_w64(mine != kNone);
+    while (cand) {
+        const int32_t tc = w0 + __ffsll((unsigned long long)cand) - 1;
+        cand &= cand - 1;
+        const int32_t ic = i0 + tc;                    // < n: only real positions have keys
+        const int64_t kc = K[tc + W + 1];
+        const int64_t gc = kc >> kOffBits;
+        const int32_t oc = (int32_t)(kc & kOffMask);
+        const int32_t span = (oc + 1) + (W + 1);
+        bool better = false;
+        for (int32_t j0 = 0; j0 < span && !better; j0 += kWave) {
+            const int32_t j = j0 + lane;
+            bool b = false;
+            if (j < span) {
+                const bool ahead = j <= oc;
+                const int32_t d = ahead ? j + 1 : oc - j;   // ahead: 1 .. o + 1; behind: -1 .. -(W + 1)
+                const int64_t ku = K[tc + W + 1 + d];
+                if (ku != kNone && (ahead || (int32_t)(ku & kOffMask) + 1 >= -d)) {
+                    int32_t u = ic + d;                    // W + 1 < n: one wrap at most
+                    u += u < 0 ? n : 0;
+                    u -= u >= n ? n : 0;
+                    const int64_t gu = ku >> kOffBits;
+                    b = gu < gc || (gu == gc && u < ic);
+                }
+            }
+            better = __builtin_amdgcn_ballot_w64(b) != 0;
+        }
+        if (!better && lane == 0) {
+            const int32_t e = atomicAdd(&list_count[s], 1);
+            if (e < list_cap) list[(int64_t)s * list_cap + e] = ic;
+            atomicAdd(round_moves, 1);
+        }
     }
 }
 
@@ -265,7 +302,7 @@ __global__ __launch_bounds__(kT) void k_two_opt_apply(
             }
         // keys of positions i - W .. i + o read a changed position: mark their
         // tiles.  The cyclic range is one or two linear pieces; each covers at
-        // most count / kT + 2 tiles, so 64 lanes suffice (count <= 2W + 1).
+        // most count / kTE + 2 tiles, so 64 lanes suffice (count <= 2W + 1).
         const int32_t first = i - W < 0 ? i - W + n : i - W;
         const int32_t count = W + o + 1;
         const int32_t last = first + count - 1;   // < 2n
@@ -275,8 +312,8 @@ __global__ __launch_bounds__(kT) void k_two_opt_apply(
             b1 = n - 1;
             b2 = -1;
         }
-        const int32_t t1 = a1 / kT, nt1 = b1 / kT - t1 + 1;
-        const int32_t nt2 = b2 >= 0 ? b2 / kT + 1 : 0;
+        const int32_t t1 = a1 / kTE, nt1 = b1 / kTE - t1 + 1;
+        const int32_t nt2 = b2 >= 0 ? b2 / kTE + 1 : 0;
         if (lane < nt1)
             dirty_next[(int64_t)s * tiles + t1 + lane] = 1u;
         else if (lane < nt1 + nt2)
@@ -294,7 +331,7 @@ struct TwoOptLayout {
     TwoOptLayout(int32_t n, int32_t m, int32_t batch)
     {
         auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
-        tiles = (n + kT - 1) / kT;
+        tiles = (n + kTE - 1) / kTE;   // evaluation tiles (dirty flags)
         list_cap = n / 4 + 1;   // taken spans are disjoint, each >= 4 positions
         sel = 0;
         ctl = up((size_t)m * 4);
@@ -357,7 +394,8 @@ extern "C" int aco_two_opt(const int32_t *xy, int32_t n, int32_t m, int32_t *tou
     const int32_t W = window < n / 2 ? window : n / 2;   // each edge pair from its nearer side
     aco_two_opt_stats_t out{selected, 1, 0, 0, 0};
     if (selected > 0 && W >= 2) {
-        const size_t lds_eval = (size_t)(kT + W + 2) * sizeof(int2) + (size_t)(kT + W + 1) * 4;
+        const size_t lds_eval = (size_t)(kTE + W + 2) * sizeof(int2) + (size_t)(kTE + W + 1) * 4;
+        const unsigned acc_tiles = blocks_for(n, kT);
         const size_t lds_acc = (size_t)(kT + 2 * W + 2) * sizeof(int64_t);
         for (int32_t c0 = 0; c0 < selected; c0 += batch) {
             const int32_t S = selected - c0 < batch ? selected - c0 : batch;
@@ -379,7 +417,7 @@ extern "C" int aco_two_opt(const int32_t *xy, int32_t n, int32_t m, int32_t *tou
                     k_two_opt_eval<<<dim3(lay.tiles, S), kT, lds_eval, st>>>(
                         xy, tours, ants, n, W, lay.tiles, cur, keys, list_count);
                     ACO_LAUNCH_CHECK("k_two_opt_eval");
-                    k_two_opt_accept<<<dim3(lay.tiles, S), kT, lds_acc, st>>>(
+                    k_two_opt_accept<<<dim3(acc_tiles, S), kT, lds_acc, st>>>(
                         keys, n, W, list, lay.list_cap, list_count, round_moves + b);
                     ACO_LAUNCH_CHECK("k_two_opt_accept");
                     // after max_rounds rounds, one more look only decides convergence
