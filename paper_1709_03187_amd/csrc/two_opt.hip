@@ -98,6 +98,60 @@ __device__ __forceinline__ int64_t best_move(const int2 *P, const int32_t *L, in
     }
 }
 
+template <bool kSmall>
+__device__ __forceinline__ int64_t dist_t(int2 p, int2 q)
+{
+    if constexpr (kSmall)
+        return d_small(p, q);
+    else
+        return d_int(p, q);
+}
+
+__device__ __forceinline__ int64_t move_key(int64_t g, int32_t o)
+{
+    return g < 0 ? g * (1 << kOffBits) + o : kNone;
+}
+
+// Every move of one position qf by the whole wave (lane l takes offsets
+// 2 + l, 2 + l + 64, ...), reduced to the wave's minimum key.
+template <bool kSmall>
+__device__ __forceinline__ int64_t one_position(const int2 *P, const int32_t *L, int32_t qf,
+                                                int32_t W, int lane)
+{
+    const int2 a = P[qf], b = P[qf + 1];
+    const int64_t lq = L[qf];
+    int64_t best = kNone;
+    for (int32_t o = 2 + lane; o <= W; o += kWave) {
+        const int64_t k = move_key(dist_t<kSmall>(a, P[qf + o]) + dist_t<kSmall>(b, P[qf + o + 1]) -
+                                       lq - L[qf + o],
+                                   o);
+        best = k < best ? k : best;
+    }
+    // signed order through the unsigned DPP minimum: flip the sign bit
+    return (int64_t)(wave_min_u64_dpp((uint64_t)best ^ (1ull << 63)) ^ (1ull << 63));
+}
+
+// The moves of position q whose far edge changed: x = q + o in the wave's list
+// of positions with C2[x] set, folded into `best` (the kept key).
+template <bool kSmall>
+__device__ __forceinline__ int64_t changed_moves(const int2 *P, const int32_t *L,
+                                                 const int16_t *list, int32_t cnt, int32_t q,
+                                                 int32_t W, int64_t best)
+{
+    const int2 a = P[q], b = P[q + 1];
+    const int64_t lq = L[q];
+    for (int32_t e = 0; e < cnt; ++e) {
+        const int32_t x = list[e];
+        const int32_t o = x - q;
+        if (o >= 2 && o <= W) {
+            const int64_t k =
+                move_key(dist_t<kSmall>(a, P[x]) + dist_t<kSmall>(b, P[x + 1]) - lq - L[x], o);
+            best = k < best ? k : best;
+        }
+    }
+    return best;
+}
+
 // Participating ants, in increasing order: one workgroup, wave ballots.
 __global__ __launch_bounds__(kT) void k_two_opt_select(uint64_t seed, uint32_t iteration,
                                                        int32_t m, uint64_t thr, int32_t *sel,
@@ -133,8 +187,10 @@ __global__ __launch_bounds__(kT) void k_two_opt_select(uint64_t seed, uint32_t i
     if (threadIdx.x == 0) *count = base;
 }
 
-// Dirty flags: buffer 0 all set (round 0 evaluates every tile), buffer 1 clear.
-__global__ void k_two_opt_init(uint32_t *dirty, int32_t tiles, int32_t batch, int32_t S)
+// Dirty flags: buffer 0 all set (round 0 evaluates every tile), buffer 1
+// clear; change stamps of the S tours' positions: never changed.
+__global__ void k_two_opt_init(uint32_t *dirty, int32_t tiles, int32_t batch, int32_t S,
+                               int32_t *stamp, int64_t stamps)
 {
     const int64_t per = (int64_t)S * tiles;
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < per;
@@ -142,6 +198,9 @@ __global__ void k_two_opt_init(uint32_t *dirty, int32_t tiles, int32_t batch, in
         dirty[q] = 1u;
         dirty[(int64_t)batch * tiles + q] = 0u;
     }
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < stamps;
+         q += (int64_t)gridDim.x * blockDim.x)
+        stamp[q] = -2;
 }
 
 __global__ void k_two_opt_zero(int32_t *p, int32_t count)
@@ -150,15 +209,60 @@ __global__ void k_two_opt_zero(int32_t *p, int32_t count)
 }
 
 // Best move of every position of the dirty tiles.  Grid (tiles, S).
+//
+// Round 0 evaluates every move.  Later rounds know which positions the
+// previous round changed (stamp == round - 1): a move's gain depends only on
+// the cities at positions q, q + 1, q + o, q + o + 1, so with C2[x] = "x or
+// x + 1 changed" a position q is re-evaluated in full when C2[q] (its own
+// edge) or C2[q + o_best] (its kept best move) is set, and otherwise only its
+// moves with C2[q + o] set are recomputed and folded into the kept key.  Full
+// positions are done one at a time by the whole wave.  A wave runs every
+// move of all its lanes instead (round 0, or when that is cheaper): that costs
+// W' distances per lane, the other way 2 per listed position plus
+// 2 ceil((W' - 1) / 64) per full position.
+
+template <bool kSmall>
+__device__ __forceinline__ int64_t eval_wave(const int2 *P, const int32_t *L, const uint8_t *C2,
+                                             int16_t *list, int32_t q0, int lane, int32_t W,
+                                             bool first, bool valid, int64_t old)
+{
+    const int32_t q = q0 + lane;
+    const bool full = first || (valid && (C2[q] || (old != kNone && C2[q + (int32_t)(old & kOffMask)])));
+    const uint64_t fmask = __builtin_amdgcn_ballot_w64(full && valid);
+    if (first) return best_move<kSmall>(P, L, q, W);
+    // positions x = q0 + 2 .. q0 + 62 + W with C2[x] set, in order
+    int32_t cnt = 0;
+    for (int32_t x0 = q0 + 2; x0 <= q0 + kPosPerWave - 1 + W; x0 += kWave) {
+        const int32_t x = x0 + lane;
+        const bool c = x <= q0 + kPosPerWave - 1 + W && C2[x];
+        const uint64_t bal = __builtin_amdgcn_ballot_w64(c);
+        if (c) list[cnt + __popcll(bal & ((1ull << lane) - 1ull))] = (int16_t)x;
+        cnt += __popcll(bal);
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int32_t per_full = 2 * ((W - 2) / kWave + 1);
+    if (2 * cnt + __popcll(fmask) * per_full >= W) return best_move<kSmall>(P, L, q, W);
+    int64_t key = changed_moves<kSmall>(P, L, list, cnt, q, W, full ? kNone : old);
+    for (uint64_t f = fmask; f; f &= f - 1) {
+        const int fl = __ffsll((unsigned long long)f) - 1;
+        const int64_t k = one_position<kSmall>(P, L, q0 + fl, W, lane);
+        key = lane == fl ? k : key;
+    }
+    return key;
+}
+
 __global__ __launch_bounds__(kT) void k_two_opt_eval(const int32_t *__restrict__ xy,
                                                      const int32_t *__restrict__ tours,
                                                      const int32_t *__restrict__ ants, int32_t n,
-                                                     int32_t W, int32_t tiles,
+                                                     int32_t W, int32_t tiles, int32_t round,
+                                                     const int32_t *__restrict__ stamp,
                                                      uint32_t *__restrict__ dirty_cur,
                                                      int64_t *__restrict__ keys,
                                                      int32_t *__restrict__ list_count)
 {
-    extern __shared__ int2 P[];   // coordinates of positions i0 .. i0 + kTE + W + 1
+    // LDS: P int2 [np] (coordinates of positions i0 .. i0 + kTE + W + 1),
+    // L int32 [np], per-wave lists int16 [4][kPosPerWave + W], C2 uint8 [np]
+    extern __shared__ int2 P[];
     __shared__ uint32_t go;
     __shared__ int32_t box[4];    // min x, max x, min y, max y of the tile
     const int32_t s = blockIdx.y, tile = blockIdx.x;
@@ -174,11 +278,16 @@ __global__ __launch_bounds__(kT) void k_two_opt_eval(const int32_t *__restrict__
     if (!go) return;
     const int32_t np = kTE + W + 2;
     int32_t *L = (int32_t *)(P + np);     // L[q] = d(P[q], P[q + 1])
+    int16_t *lists = (int16_t *)(L + np);
+    uint8_t *C2 = (uint8_t *)(lists + (kT / kWave) * (kPosPerWave + W));
     const int32_t *tour = tours + (int64_t)ants[s] * n;
+    const int32_t *st = stamp + (int64_t)s * n;
     const int32_t i0 = tile * kTE;
+    const bool first = round == 0;
     int32_t x0 = INT32_MAX, x1 = INT32_MIN, y0 = INT32_MAX, y1 = INT32_MIN;
     for (int32_t q = threadIdx.x; q < np; q += kT) {
-        const int32_t c = tour[((int64_t)i0 + q) % n];
+        const int64_t pos = ((int64_t)i0 + q) % n;
+        const int32_t c = tour[pos];
         const int64_t cc = (uint32_t)c < (uint32_t)n ? c : 0;   // a tour is a permutation
         const int2 pt = make_int2(xy[2 * cc], xy[2 * cc + 1]);
         P[q] = pt;
@@ -186,6 +295,10 @@ __global__ __launch_bounds__(kT) void k_two_opt_eval(const int32_t *__restrict__
         x1 = max(x1, pt.x);
         y0 = min(y0, pt.y);
         y1 = max(y1, pt.y);
+        if (!first && q < np - 1) {
+            const int64_t pos1 = pos + 1 == n ? 0 : pos + 1;
+            C2[q] = (st[pos] == round - 1 || st[pos1] == round - 1) ? 1 : 0;
+        }
     }
     atomicMin(&box[0], x0);
     atomicMax(&box[1], x1);
@@ -194,13 +307,18 @@ __global__ __launch_bounds__(kT) void k_two_opt_eval(const int32_t *__restrict__
     __syncthreads();
     for (int32_t q = threadIdx.x; q < np - 1; q += kT) L[q] = (int32_t)d_int(P[q], P[q + 1]);
     __syncthreads();
-    // whole waves run the loop (lane l + 1 feeds lane l); coordinates spanning
+    // whole waves run the loops (lane l + 1 feeds lane l); coordinates spanning
     // less than 2^21 in both axes make every difference small
     const int lane = lane_id();
-    const int32_t q = (int32_t)(threadIdx.x / kWave) * kPosPerWave + lane, i = i0 + q;
+    const int32_t w = (int32_t)(threadIdx.x / kWave);
+    const int32_t q0 = w * kPosPerWave, i = i0 + q0 + lane;
+    const bool valid = lane < kPosPerWave && i < n;
+    const int64_t old = (!first && valid) ? keys[(int64_t)s * n + i] : kNone;
+    int16_t *list = lists + w * (kPosPerWave + W);
     const bool small = (int64_t)box[1] - box[0] < (1 << 21) && (int64_t)box[3] - box[2] < (1 << 21);
-    const int64_t key = small ? best_move<true>(P, L, q, W) : best_move<false>(P, L, q, W);
-    if (lane < kPosPerWave && i < n) keys[(int64_t)s * n + i] = key;
+    const int64_t key = small ? eval_wave<true>(P, L, C2, list, q0, lane, W, first, valid, old)
+                              : eval_wave<false>(P, L, C2, list, q0, lane, W, first, valid, old);
+    if (valid) keys[(int64_t)s * n + i] = key;
 }
 
 // A position's move is taken when no overlapping move is better by (g, position).
@@ -269,8 +387,9 @@ __global__ __launch_bounds__(kT) void k_two_opt_accept(const int64_t *__restrict
 __global__ __launch_bounds__(kT) void k_two_opt_apply(
     const int64_t *__restrict__ keys, const int32_t *__restrict__ list, int32_t list_cap,
     const int32_t *__restrict__ list_count, const int32_t *__restrict__ ants, int32_t n, int32_t W,
-    int32_t tiles, int32_t *__restrict__ tours, int64_t *__restrict__ lengths,
-    uint8_t *__restrict__ slots, uint32_t *__restrict__ dirty_next, int64_t *__restrict__ gain_sum)
+    int32_t tiles, int32_t round, int32_t *__restrict__ tours, int64_t *__restrict__ lengths,
+    uint8_t *__restrict__ slots, int32_t *__restrict__ stamp, uint32_t *__restrict__ dirty_next,
+    int64_t *__restrict__ gain_sum)
 {
     const int32_t s = blockIdx.y;
     const int lane = lane_id();
@@ -292,6 +411,8 @@ __global__ __launch_bounds__(kT) void k_two_opt_apply(
             const int32_t v1 = tour[p1], v2 = tour[p2];
             tour[p1] = v2;
             tour[p2] = v1;
+            stamp[(int64_t)s * n + p1] = round;   // the cities at p1 and p2 changed
+            stamp[(int64_t)s * n + p2] = round;
         }
         // incoming edges of positions i + 1 .. i + o + 1 changed
         if (slots)
@@ -327,7 +448,7 @@ __global__ __launch_bounds__(kT) void k_two_opt_apply(
 
 struct TwoOptLayout {
     int32_t tiles, list_cap;
-    size_t sel, ctl, keys, list, dirty, total;
+    size_t sel, ctl, keys, list, dirty, stamp, total;
     TwoOptLayout(int32_t n, int32_t m, int32_t batch)
     {
         auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
@@ -339,7 +460,8 @@ struct TwoOptLayout {
         keys = ctl + up(8 + 4 + 4 * kRoundsPerSync + 4 * (size_t)batch);
         list = keys + up((size_t)batch * n * 8);
         dirty = list + up((size_t)batch * list_cap * 4);
-        total = dirty + up((size_t)2 * batch * tiles * 4);
+        stamp = dirty + up((size_t)2 * batch * tiles * 4);
+        total = stamp + up((size_t)batch * n * 4);
     }
 };
 
@@ -382,6 +504,7 @@ extern "C" int aco_two_opt(const int32_t *xy, int32_t n, int32_t m, int32_t *tou
     int64_t *keys = (int64_t *)(base + lay.keys);
     int32_t *list = (int32_t *)(base + lay.list);
     uint32_t *dirty = (uint32_t *)(base + lay.dirty);
+    int32_t *stamp = (int32_t *)(base + lay.stamp);
 
     const uint64_t thr = (uint64_t)std::nearbyint(std::ldexp(p, 32));
     k_two_opt_select<<<1, kT, 0, st>>>(seed, (uint32_t)iteration, m, thr, sel, sel_count,
@@ -394,14 +517,16 @@ extern "C" int aco_two_opt(const int32_t *xy, int32_t n, int32_t m, int32_t *tou
     const int32_t W = window < n / 2 ? window : n / 2;   // each edge pair from its nearer side
     aco_two_opt_stats_t out{selected, 1, 0, 0, 0};
     if (selected > 0 && W >= 2) {
-        const size_t lds_eval = (size_t)(kTE + W + 2) * sizeof(int2) + (size_t)(kTE + W + 1) * 4;
+        const size_t np = (size_t)(kTE + W + 2);
+        const size_t lds_eval = np * sizeof(int2) + np * 4 +
+                                (size_t)(kT / kWave) * (kPosPerWave + W) * 2 + np;
         const unsigned acc_tiles = blocks_for(n, kT);
         const size_t lds_acc = (size_t)(kT + 2 * W + 2) * sizeof(int64_t);
         for (int32_t c0 = 0; c0 < selected; c0 += batch) {
             const int32_t S = selected - c0 < batch ? selected - c0 : batch;
             const int32_t *ants = sel + c0;
-            k_two_opt_init<<<blocks_for((int64_t)S * lay.tiles, 256), 256, 0, st>>>(
-                dirty, lay.tiles, batch, S);
+            k_two_opt_init<<<blocks_for((int64_t)S * n, 256), 256, 0, st>>>(
+                dirty, lay.tiles, batch, S, stamp, (int64_t)S * n);
             ACO_LAUNCH_CHECK("k_two_opt_init");
             int64_t r = 0, improving = 0;
             bool done = false, converged = true;
@@ -415,7 +540,8 @@ extern "C" int aco_two_opt(const int32_t *xy, int32_t n, int32_t m, int32_t *tou
                     uint32_t *cur = dirty + (size_t)(rr & 1) * batch * lay.tiles;
                     uint32_t *nxt = dirty + (size_t)((rr + 1) & 1) * batch * lay.tiles;
                     k_two_opt_eval<<<dim3(lay.tiles, S), kT, lds_eval, st>>>(
-                        xy, tours, ants, n, W, lay.tiles, cur, keys, list_count);
+                        xy, tours, ants, n, W, lay.tiles, (int32_t)rr, stamp, cur, keys,
+                        list_count);
                     ACO_LAUNCH_CHECK("k_two_opt_eval");
                     k_two_opt_accept<<<dim3(acc_tiles, S), kT, lds_acc, st>>>(
                         keys, n, W, list, lay.list_cap, list_count, round_moves + b);
@@ -423,8 +549,8 @@ extern "C" int aco_two_opt(const int32_t *xy, int32_t n, int32_t m, int32_t *tou
                     // after max_rounds rounds, one more look only decides convergence
                     if (max_rounds == 0 || rr < max_rounds) {
                         k_two_opt_apply<<<dim3(kApplyBlocks, S), kT, 0, st>>>(
-                            keys, list, lay.list_cap, list_count, ants, n, W, lay.tiles, tours,
-                            lengths, slots, nxt, gain_sum);
+                            keys, list, lay.list_cap, list_count, ants, n, W, lay.tiles,
+                            (int32_t)rr, tours, lengths, slots, stamp, nxt, gain_sum);
                         ACO_LAUNCH_CHECK("k_two_opt_apply");
                     }
                 }
