@@ -100,6 +100,15 @@ def test_validation_before_any_device_call(L):
                      None) == aco.ACO_ERR_INVALID_ARG
     assert L.aco_run(None, 100, None, None, None, None, None, None, 0,
                      None) == aco.ACO_ERR_INVALID_ARG
+    # windowed 2-opt: window, p, batch, round cap and NULL arrays, all before the GPU
+    st = aco.AcoTwoOptStats()
+    for window, p, batch, rounds in ((0, 0.5, 1, 0), (2049, 0.5, 1, 0), (10, 1.5, 1, 0),
+                                     (10, float("nan"), 1, 0), (10, 0.5, 0, 0), (10, 0.5, 1, -1),
+                                     (10, 0.5, 1, 0)):
+        assert L.aco_two_opt(None, 100, 4, None, None, None, window, p, 1, 0, rounds, batch,
+                             C.byref(st), None, 0, None) == aco.ACO_ERR_INVALID_ARG
+    assert L.aco_two_opt_workspace_bytes(200000, 1024, 8) >= 8 * 200000 * 8
+    assert L.aco_two_opt_workspace_bytes(0, 1, 1) == 0
 
 
 def test_no_oracle_in_product_path():
