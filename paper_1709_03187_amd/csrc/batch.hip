@@ -63,6 +63,7 @@ __device__ __forceinline__ GridView batch_grid(const BatchState &S, int b)
     g.ext_stride = kBatchExt;
     g.pinv = nullptr;     // batched colonies work on city indices
     g.ext_pos = nullptr;
+    g.ext_pos_stride = 0;
     return g;
 }
 
@@ -144,6 +145,7 @@ __global__ __launch_bounds__(kGridThreads) void k_b_grid(BatchState S)
         H.n = n;
         H.cap = 3 * n + 3;
         H.kx = ext_width(n);
+        H.kxp = 0;   // no table by position: the batch works on city indices
         S.hdr[b] = H;
     }
     __syncthreads();

@@ -118,30 +118,33 @@ __global__ void k_grid_scatter(const int32_t *__restrict__ xy, GridHdr h, int32_
 // ------------------------------------------------------------------ k-NN build
 
 // One thread per city, cities taken in grid order so that a wave works on
-// neighbouring cities.  Each thread scans square blocks of cells of growing
-// radius (1, 3, 7, ...) around its city and keeps the k smallest keys (d, j)
-// sorted in LDS (interleaved by thread to avoid bank conflicts); it stops once
-// every point outside the searched block is farther than the k-th distance.
-constexpr int kKnnThreads = 64;
+// neighbouring cities.  Each thread scans rings of cells of growing radius
+// around its city and keeps the kxp smallest keys (d, j) in an LDS heap
+// (interleaved by thread to avoid bank conflicts); it stops once every point
+// outside the searched block is farther than the kxp-th distance.
+// The candidate list (k), the table by city (kx) and the table by position
+// (kxp) are prefixes of that list.  32 threads: a 256-entry list per thread
+// fits the workgroup's 64 KB.
+constexpr int kKnnThreads = 32;
 
 __global__ __launch_bounds__(kKnnThreads) void k_knn(void *grid, int32_t k, int32_t *nn,
                                                       int32_t *nnd)
 {
-    extern __shared__ uint64_t lists[];   // [kx][kKnnThreads]
+    extern __shared__ uint64_t lists[];   // [kxp][kKnnThreads]
     const GridView g = grid_view(grid);
-    const int kx = g.h.kx;                // k <= kx: the candidate list is the table's prefix
+    const int kx = g.h.kx, kxp = g.h.kxp;   // k <= kx <= kxp
     int32_t *ext = (int32_t *)g.ext;
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= g.h.n) return;
     uint64_t *L = lists + threadIdx.x;
     const int4 me = g.pts[p];
-    knn_city(g, me, kx, L, kKnnThreads);
-    const int64_t row = (int64_t)me.z * k, xrow = (int64_t)me.z * kx, prow = p * kx;
+    knn_city_wide(g, me, kxp, L, kKnnThreads);
+    const int64_t row = (int64_t)me.z * k, xrow = (int64_t)me.z * kx, prow = p * kxp;
     int32_t *ext_pos = (int32_t *)g.ext_pos;
-    for (int r = 0; r < kx; ++r) {
+    for (int r = 0; r < kxp; ++r) {
         const uint64_t key = L[(int64_t)r * kKnnThreads];
-        ext[xrow + r] = (int32_t)(uint32_t)key;
         ext_pos[prow + r] = g.pinv[(uint32_t)key];
+        if (r < kx) ext[xrow + r] = (int32_t)(uint32_t)key;
         if (r < k) {
             nn[row + r] = (int32_t)(uint32_t)key;
             nnd[row + r] = (int32_t)(key >> 32);
@@ -266,6 +269,7 @@ int build_grid(const int32_t *xy, int32_t n, void *grid, size_t grid_bytes, hipS
     h.n = n;
     h.cap = (int32_t)GridLayout::cap_for(n);
     h.kx = ext_width(n);
+    h.kxp = ext_pos_width(n);
     if ((int64_t)h.gw * h.gh + 1 > h.cap)
         return fail(ACO_ERR_HIP, "grid sizing error (%d x %d cells)", h.gw, h.gh);
     int32_t *cell_start = (int32_t *)(gb + lay.cell_start);
@@ -304,7 +308,13 @@ extern "C" int aco_build_candidates(const int32_t *xy, int32_t n, int32_t k, dou
     hipStream_t st = as_stream(stream);
     int rc = build_grid(xy, n, grid, grid_bytes, st);
     if (rc != ACO_OK) return rc;
-    const size_t lds = (size_t)ext_width(n) * kKnnThreads * sizeof(uint64_t);
+    const size_t lds = (size_t)ext_pos_width(n) * kKnnThreads * sizeof(uint64_t);
+    if (lds > max_lds_per_block())
+        return fail(ACO_ERR_UNSUPPORTED, "neighbour lists of %zu bytes exceed LDS (%zu)", lds,
+                    max_lds_per_block());
+    if (lds > 65536)
+        ACO_HIP_CHECK(hipFuncSetAttribute((const void *)k_knn,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     k_knn<<<blocks_for(n, kKnnThreads), kKnnThreads, lds, st>>>(grid, k, nn, nnd);
     ACO_LAUNCH_CHECK("k_knn");
     const int64_t nk = (int64_t)n * k;

@@ -368,6 +368,77 @@ __device__ inline void knn_city(const GridView &g, const int4 me, int kx, uint64
     }
 }
 
+// The same list for a wide table (hundreds of entries), by one thread: a
+// max-heap of the kx smallest keys in LDS at L[0], L[ls], ... (O(log kx) per
+// kept point instead of a shift of the sorted list), rings of cells one radius
+// at a time (the doubling blocks above would read many more points than a
+// wide list needs), the same stopping rule against the heap's root, and a heap
+// sort into (d, index) order at the end.  Requires kx <= (number of other
+// cities).
+__device__ inline void knn_heap_down(uint64_t *L, int ls, int cnt, int i, uint64_t key)
+{
+    for (;;) {
+        int c = 2 * i + 1;
+        if (c >= cnt) break;
+        uint64_t cv = L[(int64_t)c * ls];
+        if (c + 1 < cnt) {
+            const uint64_t c2 = L[(int64_t)(c + 1) * ls];
+            if (c2 > cv) {
+                cv = c2;
+                ++c;
+            }
+        }
+        if (cv <= key) break;
+        L[(int64_t)i * ls] = cv;
+        i = c;
+    }
+    L[(int64_t)i * ls] = key;
+}
+
+__device__ inline void knn_city_wide(const GridView &g, const int4 me, int kx, uint64_t *L, int ls)
+{
+    const GridHdr &h = g.h;
+    const int gx = cell_x(h, me.x), gy = cell_y(h, me.y);
+    int cnt = 0;
+    for (int r = 1, rin = -1;; rin = r, ++r) {
+        const int nslots = 2 * (2 * r + 1);
+        for (int s = 0; s < nslots; ++s) {
+            int row, xa, xb;
+            if (!block_slot(h, gx, gy, rin, r, s, row, xa, xb)) continue;
+            const int a = g.cell_start[(int64_t)row * h.gw + xa];
+            const int b = g.cell_start[(int64_t)row * h.gw + xb + 1];
+            for (int q = a; q < b; ++q) {
+                const int4 pt = g.pts[q];
+                if (pt.z == me.z) continue;
+                const uint64_t key =
+                    ((uint64_t)(uint32_t)nint_sqrt(sq_dist(me.x, me.y, pt.x, pt.y)) << 32) |
+                    (uint32_t)pt.z;
+                if (cnt < kx) {
+                    int i = cnt++;   // sift up
+                    while (i > 0) {
+                        const int pi = (i - 1) >> 1;
+                        const uint64_t pv = L[(int64_t)pi * ls];
+                        if (pv >= key) break;
+                        L[(int64_t)i * ls] = pv;
+                        i = pi;
+                    }
+                    L[(int64_t)i * ls] = key;
+                } else if (key < L[0]) {
+                    knn_heap_down(L, ls, kx, 0, key);
+                }
+            }
+        }
+        int64_t bound;
+        if (!outside_bound(h, me.x, me.y, gx, gy, r, bound)) break;
+        if (cnt == kx && bound > (int64_t)(L[0] >> 32)) break;
+    }
+    for (int end = cnt - 1; end > 0; --end) {   // heap sort: ascending keys
+        const uint64_t top = L[0], last = L[(int64_t)end * ls];
+        L[(int64_t)end * ls] = top;
+        knn_heap_down(L, ls, end, 0, last);
+    }
+}
+
 // The nearest-neighbour tour from city 0 by one wave: the first unvisited
 // candidate of the current city when there is one (candidate keys are smaller
 // than all others), else the nearest unvisited city (64-NN table, then grid).
@@ -429,7 +500,7 @@ __device__ inline void nn_tour_positions(const GridView &g, int32_t n, const Vis
 {
     const int lane = lane_id();
     vis.clear(n, lane);
-    const int kFirst = g.h.kx < 16 ? g.h.kx : 16;
+    const int kFirst = g.h.kxp < 16 ? g.h.kxp : 16;
     const VisitedByPosition vp{vis.w};
     int32_t c = g.pinv[0];
     if (lane == 0) vis.set(c);
@@ -438,7 +509,7 @@ __device__ inline void nn_tour_positions(const GridView &g, int32_t n, const Vis
         int32_t j = 0;
         bool unv = false;
         if (lane < kFirst) {
-            j = g.ext_pos[(int64_t)c * g.ext_stride + lane];
+            j = g.ext_pos[(int64_t)c * g.ext_pos_stride + lane];
             unv = !vis.test(j);
         }
         const uint64_t bal = __ballot(unv);

@@ -160,7 +160,8 @@ struct GridHdr {
     int32_t ncell;    // gw * gh
     int32_t n;        // cities
     int32_t cap;      // capacity of cell_start (>= ncell + 1)
-    int32_t kx;       // width of the extended neighbour table
+    int32_t kx;       // width of the extended neighbour table by city
+    int32_t kxp;      // width of the extended neighbour table by position (0: none)
 };
 
 // Extended neighbour table: the kx = min(64, n - 1) nearest cities of every
@@ -169,6 +170,14 @@ struct GridHdr {
 // whenever one of those kx cities is still unvisited.
 constexpr int kExtWidth = 64;
 __host__ __device__ inline int ext_width(int64_t n) { return n - 1 < kExtWidth ? (int)(n - 1) : kExtWidth; }
+// The single-instance construction keeps a wider table by position: the
+// nearest unvisited city after the candidates is then found in the table far
+// more often (a grid search costs many dependent reads, a table row a few).
+constexpr int kExtPosWidth = 256;
+__host__ __device__ inline int ext_pos_width(int64_t n)
+{
+    return n - 1 < kExtPosWidth ? (int)(n - 1) : kExtPosWidth;
+}
 
 // A city's position is its index in `pts` (cell order).  The single-instance
 // construction works on positions, so that the cities of a run of cells in
@@ -180,7 +189,9 @@ struct GridView {
     const int32_t *ext;          // [n][ext_stride], first kx entries of a row valid
     int32_t ext_stride;
     const int32_t *pinv;         // [n] position of each city (nullptr where not built)
-    const int32_t *ext_pos;      // [n][ext_stride]: ext by position, entries positions
+    const int32_t *ext_pos;      // [n][ext_pos_stride]: the kxp nearest by position, entries
+                                 // positions (nullptr where not built)
+    int32_t ext_pos_stride;
 };
 
 // Byte layout of the grid buffer (offsets aligned to 256 bytes).
@@ -199,7 +210,7 @@ struct GridLayout {
         ext = align(pts + (size_t)n * 16);
         pinv = align(ext + (size_t)n * ext_width(n) * 4);
         ext_pos = align(pinv + (size_t)n * 4);
-        total = align(ext_pos + (size_t)n * ext_width(n) * 4);
+        total = align(ext_pos + (size_t)n * ext_pos_width(n) * 4);
     }
 };
 
@@ -215,6 +226,7 @@ __device__ __forceinline__ GridView grid_view(const void *grid)
     g.ext_stride = g.h.kx;
     g.pinv = (const int32_t *)(b + L.pinv);
     g.ext_pos = (const int32_t *)(b + L.ext_pos);
+    g.ext_pos_stride = g.h.kxp;
     return g;
 }
 
@@ -489,18 +501,22 @@ __device__ __forceinline__ int32_t fallback_position(const GridView &g, int32_t 
                                                      const VisitedByPosition &vis)
 {
     const int lane = lane_id();
-    const int kx = g.h.kx;
-    bool unv = false;
+    const int kxp = g.h.kxp;
+    const int32_t *row = g.ext_pos + (int64_t)c * g.ext_pos_stride;
     int32_t j = 0;
-    if (lane < kx) {
-        j = g.ext_pos[(int64_t)c * g.ext_stride + lane];
-        unv = !vis.test(j, 0);
+    // the row in chunks of 64, nearest first: the first unvisited entry is the
+    // nearest unvisited city
+    for (int r0 = 0; r0 < kxp; r0 += kWave) {
+        bool unv = false;
+        if (r0 + lane < kxp) {
+            j = row[r0 + lane];
+            unv = !vis.test(j, 0);
+        }
+        const uint64_t bal = __ballot(unv);
+        if (bal) return read_lane_i32(j, __ffsll((unsigned long long)bal) - 1);
     }
-    const uint64_t bal = __ballot(unv);
-    if (bal) return read_lane_i32(j, __ffsll((unsigned long long)bal) - 1);
     const int4 me = g.pts[c];
-    const int32_t jl = read_lane_i32(j, kx - 1);
-    const int4 pl = g.pts[jl];
+    const int4 pl = g.pts[row[kxp - 1]];
     const int64_t d_lo = nint_sqrt(sq_dist(me.x, me.y, pl.x, pl.y));
     const uint64_t best = wave_nearest_unvisited(g, me.x, me.y, vis, d_lo);
     if (best == ~0ull) return -1;
