@@ -94,14 +94,40 @@ struct VisBytes {
     }
 };
 
+// A tour entry once resolved: the city index and its coordinates.
+struct TourEntry {
+    int32_t city;
+    int2 p;
+};
+
+// The value of lane l - 1 (DPP wave shift right by one lane; lane 0's result
+// is not used).
+__device__ __forceinline__ int32_t from_prev_lane(int32_t v)
+{
+    return __builtin_amdgcn_update_dpp(v, v, 0x138 /* wave_shr:1 */, 0xf, 0xf, false);
+}
+
 // How an ant names cities.  By index: the batched colonies.  By position in
 // the grid's cell order: the single-instance construction, whose candidate
 // rows, 64-NN table and visited set are all by position, so that the grid
 // fallback can dismiss fully visited runs of cells with a few word reads.
 // Tours are written as city indices in both.
 struct CitySpace {
+    static constexpr bool kLoad = false;   // a step's city index needs no load
     __device__ __forceinline__ int32_t from_city(const GridView &, int32_t c) const { return c; }
     __device__ __forceinline__ int32_t to_city(const GridView &, int32_t c) const { return c; }
+    // city index of c and (kXY) its coordinates
+    __device__ __forceinline__ int32_t city_xy(const GridView &, const int32_t *xy, int32_t c,
+                                               int2 &p) const
+    {
+        p = ((const int2 *)xy)[c];
+        return c;
+    }
+    template <bool kXY>
+    __device__ __forceinline__ TourEntry fetch(const GridView &, const int32_t *xy, int32_t c) const
+    {
+        return TourEntry{c, kXY ? ((const int2 *)xy)[c] : make_int2(0, 0)};
+    }
     template <class Vis, class Visited>
     __device__ __forceinline__ int32_t fallback(const GridView &g, const int32_t *xy, int32_t c,
                                                 const Vis &, const Visited &visited) const
@@ -110,6 +136,7 @@ struct CitySpace {
     }
 };
 struct PositionSpace {
+    static constexpr bool kLoad = true;    // a position's city index is a load from pts
     __device__ __forceinline__ int32_t from_city(const GridView &g, int32_t c) const
     {
         return g.pinv[c];
@@ -117,6 +144,19 @@ struct PositionSpace {
     __device__ __forceinline__ int32_t to_city(const GridView &g, int32_t q) const
     {
         return g.pts[q].z;
+    }
+    __device__ __forceinline__ int32_t city_xy(const GridView &g, const int32_t *, int32_t q,
+                                               int2 &p) const
+    {
+        const int4 pt = g.pts[q];
+        p = make_int2(pt.x, pt.y);
+        return pt.z;
+    }
+    template <bool kXY>
+    __device__ __forceinline__ TourEntry fetch(const GridView &g, const int32_t *, int32_t q) const
+    {
+        const int4 pt = g.pts[q];
+        return TourEntry{pt.z, make_int2(pt.x, pt.y)};
     }
     template <class Visited>
     __device__ __forceinline__ int32_t fallback(const GridView &g, const int32_t *, int32_t c,
@@ -155,10 +195,13 @@ struct AntTask {
 // base + l) and the block's outputs are staged in lanes and stored together,
 // so the inner loop holds only the step itself.
 // KP is the scan width, the smallest power of two >= k.  `grid()` returns the
-// instance's GridView (used by fallback steps).
-template <int KP, bool kProb, int kSampler, class Space, class Vis, class GridFn>
-__device__ void build_ant_impl(const AntTask &T, const Vis &vis, const GridFn &grid,
-                               const Space &space)
+// instance's GridView (used by fallback steps).  With kLen the closed tour's
+// length is summed on the way, exactly: each lane adds the edges that end at
+// its staged steps (and at its share of a kept segment), one reduction at the
+// end; otherwise 0 is returned.
+template <int KP, bool kProb, int kSampler, bool kLen, class Space, class Vis, class GridFn>
+__device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn &grid,
+                                  const Space &space)
 {
     const int lane = lane_id();
     const int32_t n = T.n, k = T.k;
@@ -169,6 +212,7 @@ __device__ void build_ant_impl(const AntTask &T, const Vis &vis, const GridFn &g
     const uint32_t x0 = (uint32_t)read_lane_i32((int32_t)rnd, 0);
     const bool active = lane < k;
     const int lr = active ? lane : k - 1;   // idle lanes re-read a valid element
+    int64_t part = 0;                       // this lane's share of the tour length
 
     // PartialACO plan from words 0-2 of the block of step 0: keep the
     // lbest[s], ..., lbest[s + keep - 1] (cyclic) and rebuild n - keep cities
@@ -202,6 +246,7 @@ __device__ void build_ant_impl(const AntTask &T, const Vis &vis, const GridFn &g
         }
         // copy eight positions per lane per round, loads issued before stores
         constexpr int kU = 8;
+        int2 kprev = make_int2(0, 0);   // coordinates of kept position t0 - 1
         for (int32_t t0 = 0; t0 < keep; t0 += kU * kWave) {
             int32_t v[kU];
 #pragma unroll
@@ -220,6 +265,24 @@ __device__ void build_ant_impl(const AntTask &T, const Vis &vis, const GridFn &g
                     if constexpr (kProb) T.prob[t] = 1.0f;
                 }
             }
+            if constexpr (kLen) {
+                int2 pc[kU];
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const int32_t c = (uint32_t)v[u] < (uint32_t)n ? v[u] : 0;
+                    pc[u] = ((const int2 *)T.xy)[c];
+                }
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const int32_t t = t0 + u * kWave + lane;
+                    int2 prev = make_int2(from_prev_lane(pc[u].x), from_prev_lane(pc[u].y));
+                    if (lane == 0) prev = kprev;
+                    if (t >= 1 && t < keep)
+                        part += nint_sqrt(sq_dist(prev.x, prev.y, pc[u].x, pc[u].y));
+                    kprev.x = __builtin_amdgcn_readlane(pc[u].x, kWave - 1);
+                    kprev.y = __builtin_amdgcn_readlane(pc[u].y, kWave - 1);
+                }
+            }
         }
         const int32_t last_kept = T.lbest[(s_pos + keep - 1) % n];
         c = space.from_city(g, (uint32_t)last_kept < (uint32_t)n ? last_kept : 0);
@@ -227,7 +290,40 @@ __device__ void build_ant_impl(const AntTask &T, const Vis &vis, const GridFn &g
     }
     const int32_t first = keep == 0 ? 1 : keep;   // first constructed tour position
     const int32_t store_from = keep;             // positions written by the step loop
+    // coordinates of tour position first - 1 (the start or the last kept city)
+    // and of position 0 (for the closing edge)
+    int2 carry = make_int2(0, 0), head = make_int2(0, 0);
+    if constexpr (kLen) {
+        space.city_xy(g, T.xy, c, carry);
+        head = carry;
+        if (keep > 0) {
+            const int32_t c0 = T.lbest[s_pos];
+            head = ((const int2 *)T.xy)[(uint32_t)c0 < (uint32_t)n ? c0 : 0];
+        }
+    }
 
+    // the previous block's tour entries, stored (and their edges summed) at
+    // the end of the next block; lanes before the first stored step stand for
+    // position first - 1 (coordinates `carry`)
+    int32_t pend_city = 0, pend_x = 0, pend_y = 0;
+    bool pend_mine = false, pend_any = false;
+    int32_t pend_base = 0, pend_last = 0;
+#define ACO_FLUSH_PENDING()                                                                    \
+    do {                                                                                       \
+        if (pend_mine) T.tour[pend_base + lane] = pend_city;                                  \
+        if constexpr (kLen) {                                                                  \
+            /* edge (t - 1, t) for every stored step t >= 1 */                                 \
+            const int32_t px = pend_mine ? pend_x : carry.x, py = pend_mine ? pend_y : carry.y; \
+            int32_t qx = from_prev_lane(px), qy = from_prev_lane(py);                         \
+            if (lane == 0) {                                                                   \
+                qx = carry.x;                                                                  \
+                qy = carry.y;                                                                  \
+            }                                                                                  \
+            if (pend_mine && pend_base + lane >= 1) part += nint_sqrt(sq_dist(qx, qy, px, py)); \
+            carry.x = __builtin_amdgcn_readlane(px, pend_last - pend_base);                    \
+            carry.y = __builtin_amdgcn_readlane(py, pend_last - pend_base);                    \
+        }                                                                                      \
+    } while (0)
     CandW e = T.rows[(int64_t)c * k + lr];
     for (int32_t base = first & ~(kWave - 1); base < n; base += kWave) {
         if (base > 0) rnd = colony_draw(T.seed, T.iteration, T.ant, (uint32_t)(base + lane));
@@ -307,26 +403,52 @@ __device__ void build_ant_impl(const AntTask &T, const Vis &vis, const GridFn &g
             }
             c = jn;
         }
-        if (base + lane <= last && base + lane >= store_from) {
-            T.tour[base + lane] = space.to_city(g, st_city);
+        // records go out now; the tour entries need a load (city index and
+        // coordinates by position), so they go out one block later, when that
+        // load has long arrived, instead of stalling the wave here
+        const bool mine = base + lane <= last && base + lane >= store_from;
+        if (mine) {
             T.slots[base + lane] = (uint8_t)st_slot;
             if constexpr (kProb) T.prob[base + lane] = st_prob;
         }
+        if constexpr (!Space::kLoad && !kLen) {   // nothing to wait for
+            if (mine) T.tour[base + lane] = st_city;
+            continue;
+        }
+        if (pend_any) ACO_FLUSH_PENDING();
+        if (mine) {
+            const TourEntry te = space.template fetch<kLen>(g, T.xy, st_city);
+            pend_city = te.city;
+            pend_x = te.p.x;
+            pend_y = te.p.y;
+        }
+        pend_mine = mine;
+        pend_base = base;
+        pend_last = last;
+        pend_any = true;
     }
+    if (pend_any) ACO_FLUSH_PENDING();
+#undef ACO_FLUSH_PENDING
+    if constexpr (!kLen) return 0;
+    // the closing edge (position n - 1 to position 0), then one reduction
+    if (lane == 0) part += nint_sqrt(sq_dist(carry.x, carry.y, head.x, head.y));
+    for (int off = kWave / 2; off > 0; off >>= 1) part += __shfl_xor(part, off);
+    return part;
 }
 
 // kSampler selects the next-city rule at compile time, so each kernel holds
 // one of them only: 0 the roulette of Eq. 1; 1 Independent Roulette (Section
 // 3: the largest w_r U_r, U_r from word r mod 4 of the Philox block at
 // counter (t, ant, iteration, 1 + r / 4), ties to the lower rank).
-template <int KP, class Space = CitySpace, int kSampler = 0, class Vis, class GridFn>
-__device__ void build_ant(const AntTask &T, const Vis &vis, const GridFn &grid,
-                          const Space &space = Space())
+template <int KP, class Space = CitySpace, int kSampler = 0, bool kLen = false, class Vis,
+          class GridFn>
+__device__ int64_t build_ant(const AntTask &T, const Vis &vis, const GridFn &grid,
+                             const Space &space = Space())
 {
     if (T.prob)
-        build_ant_impl<KP, true, kSampler>(T, vis, grid, space);
+        return build_ant_impl<KP, true, kSampler, kLen>(T, vis, grid, space);
     else
-        build_ant_impl<KP, false, kSampler>(T, vis, grid, space);
+        return build_ant_impl<KP, false, kSampler, kLen>(T, vis, grid, space);
 }
 
 // The kx nearest cities of city `me` in (d, index) order, by one thread:

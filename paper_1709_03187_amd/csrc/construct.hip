@@ -7,7 +7,8 @@
 // candidates against its visited bitmask in LDS, forms the FP64 running sum of
 // the unvisited weights across lanes, and picks the first lane whose running
 // sum exceeds u * S with a ballot.  When no unvisited candidate has positive
-// weight the wave takes the nearest unvisited city (64-NN table, then grid).
+// weight the wave takes the nearest unvisited city (256-NN table, then grid).
+// The tour's length is summed exactly inside the same kernel.
 #include <cmath>
 
 #include "colony.hpp"
@@ -71,38 +72,9 @@ __global__ __launch_bounds__(kWave) void k_construct(ConstructArgs A)
     T.lbest = A.lbest ? A.lbest + (int64_t)a * A.n : nullptr;
     T.p_threshold = A.p_threshold;
     T.max_modify = A.max_modify;
-    build_ant<KP, PositionSpace, kSampler>(T, VisBits{vis}, [&]() { return grid_view(A.grid); });
-    if (lane_id() == 0) A.lengths[a] = 0;       // summed by k_tour_length
-}
-
-// Tour lengths: one block of 256 threads per (ant, chunk of 256 tour edges),
-// exact integer distances, one int64 atomic per block.
-constexpr int kLenThreads = 256;
-
-__global__ __launch_bounds__(kLenThreads) void k_tour_length(const int32_t *__restrict__ xy,
-                                                             const int32_t *__restrict__ tours,
-                                                             int32_t n, int32_t chunks,
-                                                             unsigned long long *lengths)
-{
-    __shared__ int64_t part[kLenThreads / kWave];
-    const int32_t a = blockIdx.x / chunks;
-    const int32_t t = (blockIdx.x - a * chunks) * kLenThreads + threadIdx.x;
-    int64_t d = 0;
-    if (t < n) {
-        const int32_t *T = tours + (int64_t)a * n;
-        const int32_t i = T[t], j = T[t + 1 == n ? 0 : t + 1];
-        d = nint_sqrt(sq_dist(xy[2 * (int64_t)i], xy[2 * (int64_t)i + 1], xy[2 * (int64_t)j],
-                              xy[2 * (int64_t)j + 1]));
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off);
-    if (lane_id() == 0) part[threadIdx.x / kWave] = d;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t s = 0;
-        for (int w = 0; w < kLenThreads / kWave; ++w) s += part[w];
-        atomicAdd(&lengths[a], (unsigned long long)s);
-    }
+    const int64_t len = build_ant<KP, PositionSpace, kSampler, true>(
+        T, VisBits{vis}, [&]() { return grid_view(A.grid); });
+    if (lane_id() == 0) A.lengths[a] = len;     // exact closed length
 }
 
 }  // namespace aco
@@ -159,10 +131,6 @@ static int construct(const int32_t *xy, int32_t n, int32_t k, const int32_t *nn,
                     step_prob, lbest,   p_threshold, max_modify};
     kern<<<m, kWave, lds, st>>>(A);
     ACO_LAUNCH_CHECK("k_construct");
-    const int32_t chunks = (n + kLenThreads - 1) / kLenThreads;
-    k_tour_length<<<(unsigned)((int64_t)m * chunks), kLenThreads, 0, st>>>(
-        xy, tours, n, chunks, (unsigned long long *)lengths);
-    ACO_LAUNCH_CHECK("k_tour_length");
     return ACO_OK;
 }
 
