@@ -530,7 +530,7 @@ def main():
                    "parallelism": "one ant per wavefront"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "aco_construct_tours (k_choice_info + k_construct + k_tour_length)",
+                     "kernel": "aco_construct_tours (k_choice_info + k_construct)",
                      "bytes_per_ant_step": bps,
                      "algorithmic_bytes_per_launch": construct_bytes_per_launch(n, m, k),
                      "traffic_bytes_per_launch": tb},
