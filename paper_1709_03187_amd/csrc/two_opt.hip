@@ -203,6 +203,20 @@ __global__ void k_two_opt_init(uint32_t *dirty, int32_t tiles, int32_t batch, in
         stamp[q] = -2;
 }
 
+// Coordinates in tour order of the S tours: pxy[s][p] = xy[tours[ants[s]][p]].
+__global__ void k_two_opt_coords(const int32_t *__restrict__ xy, const int32_t *__restrict__ tours,
+                                 const int32_t *__restrict__ ants, int32_t n, int32_t S,
+                                 int2 *__restrict__ pxy)
+{
+    const int64_t total = (int64_t)S * n;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = q / n, p = q - s * n;
+        const int32_t c = tours[(int64_t)ants[s] * n + p];
+        pxy[q] = ((const int2 *)xy)[(uint32_t)c < (uint32_t)n ? c : 0];   // tours are permutations
+    }
+}
+
 __global__ void k_two_opt_zero(int32_t *p, int32_t count)
 {
     for (int32_t q = threadIdx.x; q < count; q += blockDim.x) p[q] = 0;
@@ -251,9 +265,7 @@ __device__ __forceinline__ int64_t eval_wave(const int2 *P, const int32_t *L, co
     return key;
 }
 
-__global__ __launch_bounds__(kT) void k_two_opt_eval(const int32_t *__restrict__ xy,
-                                                     const int32_t *__restrict__ tours,
-                                                     const int32_t *__restrict__ ants, int32_t n,
+__global__ __launch_bounds__(kT) void k_two_opt_eval(const int2 *__restrict__ pxy, int32_t n,
                                                      int32_t W, int32_t tiles, int32_t round,
                                                      const int32_t *__restrict__ stamp,
                                                      uint32_t *__restrict__ dirty_cur,
@@ -261,7 +273,8 @@ __global__ __launch_bounds__(kT) void k_two_opt_eval(const int32_t *__restrict__
                                                      int32_t *__restrict__ list_count)
 {
     // LDS: P int2 [np] (coordinates of positions i0 .. i0 + kTE + W + 1),
-    // L int32 [np], per-wave lists int16 [4][kPosPerWave + W], C2 uint8 [np]
+    // L int32 [np], per-wave lists int16 [4][kPosPerWave + W], C2 uint8 [np],
+    // CH uint8 [np] (position changed in the previous round)
     extern __shared__ int2 P[];
     __shared__ uint32_t go;
     __shared__ int32_t box[4];    // min x, max x, min y, max y of the tile
@@ -280,42 +293,43 @@ __global__ __launch_bounds__(kT) void k_two_opt_eval(const int32_t *__restrict__
     int32_t *L = (int32_t *)(P + np);     // L[q] = d(P[q], P[q + 1])
     int16_t *lists = (int16_t *)(L + np);
     uint8_t *C2 = (uint8_t *)(lists + (kT / kWave) * (kPosPerWave + W));
-    const int32_t *tour = tours + (int64_t)ants[s] * n;
+    uint8_t *CH = C2 + np;
+    const int2 *pc = pxy + (int64_t)s * n;   // coordinates in tour order
     const int32_t *st = stamp + (int64_t)s * n;
     const int32_t i0 = tile * kTE;
     const bool first = round == 0;
     int32_t x0 = INT32_MAX, x1 = INT32_MIN, y0 = INT32_MAX, y1 = INT32_MIN;
     for (int32_t q = threadIdx.x; q < np; q += kT) {
-        const int64_t pos = ((int64_t)i0 + q) % n;
-        const int32_t c = tour[pos];
-        const int64_t cc = (uint32_t)c < (uint32_t)n ? c : 0;   // a tour is a permutation
-        const int2 pt = make_int2(xy[2 * cc], xy[2 * cc + 1]);
+        int64_t pos = (int64_t)i0 + q;
+        pos -= pos >= n ? n : 0;
+        pos = pos >= n ? pos % n : pos;   // tiles longer than the tour wrap again
+        const int2 pt = pc[pos];
         P[q] = pt;
         x0 = min(x0, pt.x);
         x1 = max(x1, pt.x);
         y0 = min(y0, pt.y);
         y1 = max(y1, pt.y);
-        if (!first && q < np - 1) {
-            const int64_t pos1 = pos + 1 == n ? 0 : pos + 1;
-            C2[q] = (st[pos] == round - 1 || st[pos1] == round - 1) ? 1 : 0;
-        }
+        if (!first) CH[q] = st[pos] == round - 1 ? 1 : 0;
     }
     atomicMin(&box[0], x0);
     atomicMax(&box[1], x1);
     atomicMin(&box[2], y0);
     atomicMax(&box[3], y1);
     __syncthreads();
-    for (int32_t q = threadIdx.x; q < np - 1; q += kT) L[q] = (int32_t)d_int(P[q], P[q + 1]);
+    // coordinates spanning less than 2^21 in both axes make every difference small
+    const bool small = (int64_t)box[1] - box[0] < (1 << 21) && (int64_t)box[3] - box[2] < (1 << 21);
+    for (int32_t q = threadIdx.x; q < np - 1; q += kT) {
+        L[q] = small ? d_small(P[q], P[q + 1]) : (int32_t)d_int(P[q], P[q + 1]);
+        if (!first) C2[q] = CH[q] | CH[q + 1];
+    }
     __syncthreads();
-    // whole waves run the loops (lane l + 1 feeds lane l); coordinates spanning
-    // less than 2^21 in both axes make every difference small
+    // whole waves run the loops (lane l + 1 feeds lane l)
     const int lane = lane_id();
     const int32_t w = (int32_t)(threadIdx.x / kWave);
     const int32_t q0 = w * kPosPerWave, i = i0 + q0 + lane;
     const bool valid = lane < kPosPerWave && i < n;
     const int64_t old = (!first && valid) ? keys[(int64_t)s * n + i] : kNone;
     int16_t *list = lists + w * (kPosPerWave + W);
-    const bool small = (int64_t)box[1] - box[0] < (1 << 21) && (int64_t)box[3] - box[2] < (1 << 21);
     const int64_t key = small ? eval_wave<true>(P, L, C2, list, q0, lane, W, first, valid, old)
                               : eval_wave<false>(P, L, C2, list, q0, lane, W, first, valid, old);
     if (valid) keys[(int64_t)s * n + i] = key;
@@ -387,9 +401,9 @@ __global__ __launch_bounds__(kT) void k_two_opt_accept(const int64_t *__restrict
 __global__ __launch_bounds__(kT) void k_two_opt_apply(
     const int64_t *__restrict__ keys, const int32_t *__restrict__ list, int32_t list_cap,
     const int32_t *__restrict__ list_count, const int32_t *__restrict__ ants, int32_t n, int32_t W,
-    int32_t tiles, int32_t round, int32_t *__restrict__ tours, int64_t *__restrict__ lengths,
-    uint8_t *__restrict__ slots, int32_t *__restrict__ stamp, uint32_t *__restrict__ dirty_next,
-    int64_t *__restrict__ gain_sum)
+    int32_t tiles, int32_t round, int32_t *__restrict__ tours, int2 *__restrict__ pxy,
+    int64_t *__restrict__ lengths, uint8_t *__restrict__ slots, int32_t *__restrict__ stamp,
+    uint32_t *__restrict__ dirty_next, int64_t *__restrict__ gain_sum)
 {
     const int32_t s = blockIdx.y;
     const int lane = lane_id();
@@ -411,6 +425,10 @@ __global__ __launch_bounds__(kT) void k_two_opt_apply(
             const int32_t v1 = tour[p1], v2 = tour[p2];
             tour[p1] = v2;
             tour[p2] = v1;
+            int2 *pc = pxy + (int64_t)s * n;
+            const int2 c1 = pc[p1], c2 = pc[p2];
+            pc[p1] = c2;
+            pc[p2] = c1;
             stamp[(int64_t)s * n + p1] = round;   // the cities at p1 and p2 changed
             stamp[(int64_t)s * n + p2] = round;
         }
@@ -448,7 +466,7 @@ __global__ __launch_bounds__(kT) void k_two_opt_apply(
 
 struct TwoOptLayout {
     int32_t tiles, list_cap;
-    size_t sel, ctl, keys, list, dirty, stamp, total;
+    size_t sel, ctl, keys, list, dirty, stamp, pxy, total;
     TwoOptLayout(int32_t n, int32_t m, int32_t batch)
     {
         auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
@@ -461,7 +479,8 @@ struct TwoOptLayout {
         list = keys + up((size_t)batch * n * 8);
         dirty = list + up((size_t)batch * list_cap * 4);
         stamp = dirty + up((size_t)2 * batch * tiles * 4);
-        total = stamp + up((size_t)batch * n * 4);
+        pxy = stamp + up((size_t)batch * n * 4);
+        total = pxy + up((size_t)batch * n * 8);
     }
 };
 
@@ -505,6 +524,7 @@ extern "C" int aco_two_opt(const int32_t *xy, int32_t n, int32_t m, int32_t *tou
     int32_t *list = (int32_t *)(base + lay.list);
     uint32_t *dirty = (uint32_t *)(base + lay.dirty);
     int32_t *stamp = (int32_t *)(base + lay.stamp);
+    int2 *pxy = (int2 *)(base + lay.pxy);
 
     const uint64_t thr = (uint64_t)std::nearbyint(std::ldexp(p, 32));
     k_two_opt_select<<<1, kT, 0, st>>>(seed, (uint32_t)iteration, m, thr, sel, sel_count,
@@ -519,7 +539,7 @@ extern "C" int aco_two_opt(const int32_t *xy, int32_t n, int32_t m, int32_t *tou
     if (selected > 0 && W >= 2) {
         const size_t np = (size_t)(kTE + W + 2);
         const size_t lds_eval = np * sizeof(int2) + np * 4 +
-                                (size_t)(kT / kWave) * (kPosPerWave + W) * 2 + np;
+                                (size_t)(kT / kWave) * (kPosPerWave + W) * 2 + 2 * np;
         const unsigned acc_tiles = blocks_for(n, kT);
         const size_t lds_acc = (size_t)(kT + 2 * W + 2) * sizeof(int64_t);
         for (int32_t c0 = 0; c0 < selected; c0 += batch) {
@@ -528,6 +548,9 @@ extern "C" int aco_two_opt(const int32_t *xy, int32_t n, int32_t m, int32_t *tou
             k_two_opt_init<<<blocks_for((int64_t)S * n, 256), 256, 0, st>>>(
                 dirty, lay.tiles, batch, S, stamp, (int64_t)S * n);
             ACO_LAUNCH_CHECK("k_two_opt_init");
+            k_two_opt_coords<<<blocks_for((int64_t)S * n, 256), 256, 0, st>>>(xy, tours, ants, n,
+                                                                              S, pxy);
+            ACO_LAUNCH_CHECK("k_two_opt_coords");
             int64_t r = 0, improving = 0;
             bool done = false, converged = true;
             while (!done) {
@@ -540,8 +563,7 @@ extern "C" int aco_two_opt(const int32_t *xy, int32_t n, int32_t m, int32_t *tou
                     uint32_t *cur = dirty + (size_t)(rr & 1) * batch * lay.tiles;
                     uint32_t *nxt = dirty + (size_t)((rr + 1) & 1) * batch * lay.tiles;
                     k_two_opt_eval<<<dim3(lay.tiles, S), kT, lds_eval, st>>>(
-                        xy, tours, ants, n, W, lay.tiles, (int32_t)rr, stamp, cur, keys,
-                        list_count);
+                        pxy, n, W, lay.tiles, (int32_t)rr, stamp, cur, keys, list_count);
                     ACO_LAUNCH_CHECK("k_two_opt_eval");
                     k_two_opt_accept<<<dim3(acc_tiles, S), kT, lds_acc, st>>>(
                         keys, n, W, list, lay.list_cap, list_count, round_moves + b);
@@ -550,7 +572,7 @@ extern "C" int aco_two_opt(const int32_t *xy, int32_t n, int32_t m, int32_t *tou
                     if (max_rounds == 0 || rr < max_rounds) {
                         k_two_opt_apply<<<dim3(kApplyBlocks, S), kT, 0, st>>>(
                             keys, list, lay.list_cap, list_count, ants, n, W, lay.tiles,
-                            (int32_t)rr, tours, lengths, slots, stamp, nxt, gain_sum);
+                            (int32_t)rr, tours, pxy, lengths, slots, stamp, nxt, gain_sum);
                         ACO_LAUNCH_CHECK("k_two_opt_apply");
                     }
                 }
