@@ -429,8 +429,9 @@ def main():
     ap.add_argument("--no-partial", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the colony would shard).", file=sys.stderr)
+        print("bench.py measures one GPU only: the colony has no multi-GPU path "
+              "(it would shard ants by index and all-reduce the int64 deposits).",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -44,7 +44,7 @@ extern "C" {
 
 #define ACO_OK 0
 #define ACO_ERR_INVALID_ARG (-1) /* a size, pointer or parameter is out of range */
-#define ACO_ERR_UNSUPPORTED (-2) /* valid, but beyond what this build supports (e.g. LDS) */
+#define ACO_ERR_UNSUPPORTED (-2) /* valid, but beyond what the library supports (e.g. LDS) */
 #define ACO_ERR_DEGENERATE (-3)  /* every city coincides: the NN tour has length 0 */
 #define ACO_ERR_WORKSPACE (-4)   /* workspace smaller than the matching *_bytes query */
 #define ACO_ERR_HIP (-5)         /* a HIP runtime call failed */
