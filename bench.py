@@ -96,7 +96,21 @@ def cpu_baseline(xy, cfg, tau0_gpu, threads, ants_per_thread=4):
     res = orc.construct(xy, nn, nnd, tau, cfg["alpha"], cfg["beta"], cfg["seed"], 0,
                         np.arange(count), threads=threads)
     dt = time.time() - t0
+    # one thread, one ant: the oracle's single-core rate
+    t1 = time.time()
+    orc.construct(xy, nn, nnd, tau, cfg["alpha"], cfg["beta"], cfg["seed"], 0, np.arange(1),
+                  threads=1)
+    one = (n - 1) / (time.time() - t1)
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return dict(value=count * (n - 1) / dt, unit="ant-steps/s", cores=threads, kind="oracle",
+                one_thread=one, cpu_model=model, cpu_count=os.cpu_count(),
                 sample=f"{count} ants of iteration 0 at n={n} (FP64, O(n) fallback), "
                        f"{dt:.1f} s; candidate lists took {t_knn:.1f} s and are not counted",
                 L_nn=L_nn, first_tour_s=t_knn + t_nn,
@@ -589,9 +603,18 @@ def main():
             "gap": ((best_len - cb["L_nn"]) / cb["L_nn"]) if oracle_has_tour else None,
             "gap_vs_oracle_nn_tour_whenever_ready": (best_len - cb["L_nn"]) / cb["L_nn"],
         }
+        comb = out.get("partial_independent_local_best_two_opt")
+        if comb is not None:
+            # the paper's combination (PartialACO, Independent Roulette, pheromone
+            # from the local bests, 2-opt) ran for the same time from set-up
+            out["equal_time"]["gpu_best_partial_ir_local_best_two_opt"] = comb["best_len"]
+            out["equal_time"]["gap_partial_ir_local_best_two_opt_vs_oracle_nn_tour"] = (
+                (comb["best_len"] - cb["L_nn"]) / cb["L_nn"])
         out["cpu_baseline_extra"] = {"tau0_matches_gpu": cb["tau0_matches_gpu"],
                                      "fallback_share": cb["fallback_share"],
-                                     "sample_best_len": cb["sample_best_len"]}
+                                     "sample_best_len": cb["sample_best_len"],
+                                     "one_thread_ant_steps_per_s": cb["one_thread"],
+                                     "cpu_model": cb["cpu_model"], "cpu_count": cb["cpu_count"]}
     print(json.dumps(out), flush=True)
 
 

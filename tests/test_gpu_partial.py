@@ -124,11 +124,14 @@ def test_one_rebuilt_city_rotates_the_local_best():
     col.construct(0)
     col.update_local_best()
     lb = _np(col.lbest).copy()
+    lb_len = _np(col.lbest_len).copy()
     col.construct_partial(1, 1.0, 1)
-    tours = _np(col.tours)
+    tours, lengths = _np(col.tours), _np(col.lengths)
     for a in range(8):
         s, partial, r = orc.partial_plan(4, 1, a, len(xy), 1.0, 1)
         np.testing.assert_array_equal(tours[a], np.roll(lb[a], -s))
+        # the length summed over the kept segment and the closing edge is the local best's
+        assert lengths[a] == lb_len[a] == orc.tour_length(xy, tours[a])
 
 
 def test_partial_full_size_sample():
