@@ -324,7 +324,12 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
             carry.y = __builtin_amdgcn_readlane(py, pend_last - pend_base);                    \
         }                                                                                      \
     } while (0)
-    CandW e = T.rows[(int64_t)c * k + lr];
+    // the next row is the guessed one (eg) or the one loaded after the draw
+    // (en); the choice between them is made at the top of the next step, so
+    // that a step whose guess missed issues its load before anything waits on
+    // the guess
+    CandW eg = T.rows[(int64_t)c * k + lr], en = eg;
+    bool hit = true;
     for (int32_t base = first & ~(kWave - 1); base < n; base += kWave) {
         if (base > 0) rnd = colony_draw(T.seed, T.iteration, T.ant, (uint32_t)(base + lane));
         // staged outputs: lane l holds step base + l (step 0 is the start city)
@@ -334,6 +339,7 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
         const int32_t last = min(base + kWave - 1, n - 1);
         for (int32_t step = max(base, first); step <= last; ++step) {
             const int idx = step - base;
+            const CandW e = hit ? eg : en;
             const int32_t j = e.city;
             const uint32_t seen = visited(j);          // every lane reads a valid word
             const bool unv = active && seen == 0u;
@@ -342,7 +348,6 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
             // the first candidate that can be chosen is the likeliest next city
             // (rows are in distance order): its row is loaded while the scan runs
             int32_t guess = -1;
-            CandW eg;
             if (any) {
                 guess = read_lane_i32(j, __ffsll((unsigned long long)any) - 1);
                 eg = T.rows[(int64_t)guess * k + lr];
@@ -391,10 +396,8 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
             // a city index is always in range here; the clamp only keeps a logic
             // error from turning into an out-of-bounds access (tests see the tour)
             jn = ((uint32_t)jn < (uint32_t)n) ? jn : start;
-            if (jn == guess)
-                e = eg;
-            else
-                e = T.rows[(int64_t)jn * k + lr];
+            hit = jn == guess;
+            if (!hit) en = T.rows[(int64_t)jn * k + lr];
             if (lane == 0) vis.set(jn);
             if (lane == idx) {
                 st_city = jn;
