@@ -454,6 +454,15 @@ __device__ int64_t build_ant(const AntTask &T, const Vis &vis, const GridFn &gri
         return build_ant_impl<KP, false, kSampler, kLen>(T, vis, grid, space);
 }
 
+// The same with the probability record fixed at compile time (kProb: T.prob
+// is written; otherwise it is ignored), for kernels that hold one variant only.
+template <int KP, bool kProb, class Space, int kSampler, bool kLen, class Vis, class GridFn>
+__device__ int64_t build_ant_fixed(const AntTask &T, const Vis &vis, const GridFn &grid,
+                                   const Space &space = Space())
+{
+    return build_ant_impl<KP, kProb, kSampler, kLen>(T, vis, grid, space);
+}
+
 // The kx nearest cities of city `me` in (d, index) order, by one thread:
 // square blocks of cells of growing radius (1, 3, 7, ...), a sorted list of
 // keys (d << 32 | city) in LDS at L[0], L[ls], L[2 ls], ...; the search stops

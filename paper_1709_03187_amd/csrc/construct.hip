@@ -52,8 +52,9 @@ struct ConstructArgs {
 };
 
 // One ant per workgroup of one wave; the visited bitmask is the workgroup's LDS.
-// kSampler: 0 the roulette of Eq. 1, 1 Independent Roulette.
-template <int KP, int kSampler>
+// kSampler: 0 the roulette of Eq. 1, 1 Independent Roulette; kProb: the step
+// probabilities are recorded (one variant per kernel keeps the step lean).
+template <int KP, int kSampler, bool kProb>
 __global__ __launch_bounds__(kWave) void k_construct(ConstructArgs A)
 {
     extern __shared__ uint32_t vis[];
@@ -72,7 +73,7 @@ __global__ __launch_bounds__(kWave) void k_construct(ConstructArgs A)
     T.lbest = A.lbest ? A.lbest + (int64_t)a * A.n : nullptr;
     T.p_threshold = A.p_threshold;
     T.max_modify = A.max_modify;
-    const int64_t len = build_ant<KP, PositionSpace, kSampler, true>(
+    const int64_t len = build_ant_fixed<KP, kProb, PositionSpace, kSampler, true>(
         T, VisBits{vis}, [&]() { return grid_view(A.grid); });
     if (lane_id() == 0) A.lengths[a] = len;     // exact closed length
 }
@@ -117,12 +118,15 @@ static int construct(const int32_t *xy, int32_t n, int32_t k, const int32_t *nn,
                                                         rows);
     ACO_LAUNCH_CHECK("k_choice_info");
     void (*kern)(ConstructArgs);
-    if (sampler == ACO_SAMPLER_INDEPENDENT)
-        kern = k <= 8 ? k_construct<8, 1> : k <= 16 ? k_construct<16, 1>
-             : k <= 32 ? k_construct<32, 1> : k_construct<64, 1>;
+    if (sampler == ACO_SAMPLER_INDEPENDENT)   // no step probabilities (checked above)
+        kern = k <= 8 ? k_construct<8, 1, false> : k <= 16 ? k_construct<16, 1, false>
+             : k <= 32 ? k_construct<32, 1, false> : k_construct<64, 1, false>;
+    else if (step_prob)
+        kern = k <= 8 ? k_construct<8, 0, true> : k <= 16 ? k_construct<16, 0, true>
+             : k <= 32 ? k_construct<32, 0, true> : k_construct<64, 0, true>;
     else
-        kern = k <= 8 ? k_construct<8, 0> : k <= 16 ? k_construct<16, 0>
-             : k <= 32 ? k_construct<32, 0> : k_construct<64, 0>;
+        kern = k <= 8 ? k_construct<8, 0, false> : k <= 16 ? k_construct<16, 0, false>
+             : k <= 32 ? k_construct<32, 0, false> : k_construct<64, 0, false>;
     if (lds > 65536)
         ACO_HIP_CHECK(hipFuncSetAttribute((const void *)kern,
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
