@@ -212,6 +212,7 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
     const uint32_t x0 = (uint32_t)read_lane_i32((int32_t)rnd, 0);
     const bool active = lane < k;
     const int lr = active ? lane : k - 1;   // idle lanes re-read a valid element
+    const uint64_t act_mask = k >= kWave ? ~0ull : (1ull << k) - 1ull;   // lanes < k
     int64_t part = 0;                       // this lane's share of the tour length
 
     // PartialACO plan from words 0-2 of the block of step 0: keep the
@@ -342,9 +343,11 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
             const CandW e = hit ? eg : en;
             const int32_t j = e.city;
             const uint32_t seen = visited(j);          // every lane reads a valid word
-            const bool unv = active && seen == 0u;
-            const bool live = unv && e.w > 0.0f;
-            const uint64_t any = __builtin_amdgcn_ballot_w64(live);
+            const bool live = active && seen == 0u && e.w > 0.0f;
+            // the same lanes as ballot(live), from single-compare ballots (no
+            // lane mask re-materialised in a vector register)
+            const uint64_t any = __builtin_amdgcn_ballot_w64(seen == 0u) &
+                                 __builtin_amdgcn_ballot_w64(e.w > 0.0f) & act_mask;
             // the first candidate that can be chosen is the likeliest next city
             // (rows are in distance order): its row is loaded while the scan runs
             int32_t guess = -1;
@@ -366,7 +369,7 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
                     const uint32_t xw = wd == 0 ? blk.x : wd == 1 ? blk.y : wd == 2 ? blk.z : blk.w;
                     const double v = live ? wv * ((double)xw * 0x1p-32) : -1.0;
                     const double vmax = read_lane_f64(wave_incl_max_f64(v, KP), k - 1);
-                    const uint64_t top = __builtin_amdgcn_ballot_w64(live && v == vmax);
+                    const uint64_t top = __builtin_amdgcn_ballot_w64(v == vmax) & any;
                     const int f = __ffsll((unsigned long long)top) - 1;
                     jn = read_lane_i32(j, f);
                     slot = (uint32_t)f;
@@ -374,24 +377,25 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
                     jn = space.fallback(g, T.xy, c, vis, visited);
                     slot = kNoSlot;
                 }
-            } else {
+            } else if (any) {
+                // S > 0 exactly when some candidate is live (each live weight is
+                // a positive FP32 value, so is their FP64 sum): the branch does
+                // not wait for the scan, and u is formed while the scan runs
+                const double u = (double)(uint32_t)read_lane_i32((int32_t)rnd, idx) * 0x1p-32;
                 const double cum = wave_incl_scan_f64(wv, KP);
                 const double S = read_lane_f64(cum, k - 1);
-                if (S > 0.0) {
-                    const uint32_t x = (uint32_t)read_lane_i32((int32_t)rnd, idx);
-                    const double target = (double)x * 0x1p-32 * S;
-                    const uint64_t hit = __builtin_amdgcn_ballot_w64(live && target < cum);
-                    // first slot whose running sum passes the target; if rounding
-                    // leaves none, the last slot that can be chosen
-                    const int f = hit ? __ffsll((unsigned long long)hit) - 1
-                                      : 63 - __clzll((long long)any);
-                    jn = read_lane_i32(j, f);
-                    slot = (uint32_t)f;
-                    if constexpr (kProb) prob = (float)(read_lane_f64(wv, f) / S);
-                } else {
-                    jn = space.fallback(g, T.xy, c, vis, visited);
-                    slot = kNoSlot;
-                }
+                const double target = u * S;
+                const uint64_t hit = __builtin_amdgcn_ballot_w64(target < cum) & any;
+                // first slot whose running sum passes the target; if rounding
+                // leaves none, the last slot that can be chosen
+                const int f = hit ? __ffsll((unsigned long long)hit) - 1
+                                  : 63 - __clzll((long long)any);
+                jn = read_lane_i32(j, f);
+                slot = (uint32_t)f;
+                if constexpr (kProb) prob = (float)(read_lane_f64(wv, f) / S);
+            } else {
+                jn = space.fallback(g, T.xy, c, vis, visited);
+                slot = kNoSlot;
             }
             // a city index is always in range here; the clamp only keeps a logic
             // error from turning into an out-of-bounds access (tests see the tour)
