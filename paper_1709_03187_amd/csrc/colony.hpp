@@ -182,7 +182,14 @@ struct AntTask {
     const int32_t *lbest = nullptr;
     uint64_t p_threshold = 0;
     int32_t max_modify = 0;
+    // Independent Roulette only: LDS for one block's uniforms, 64 steps x
+    // ir_words_per_step(k) words (filled at the start of each block of steps)
+    uint32_t *ir_words = nullptr;
 };
+
+// Words of Independent Roulette uniforms held per step: k rounded up to the
+// four words of a Philox block.
+__host__ __device__ __forceinline__ int ir_words_per_step(int k) { return (k + 3) & ~3; }
 
 // Builds one ant's tour with the whole wave (Section 2, Eq. 1).  Lane r < k
 // holds candidate r of the current city.  The critical path of a step is:
@@ -333,6 +340,19 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
     bool hit = true;
     for (int32_t base = first & ~(kWave - 1); base < n; base += kWave) {
         if (base > 0) rnd = colony_draw(T.seed, T.iteration, T.ant, (uint32_t)(base + lane));
+        if constexpr (kSampler != 0) {
+            // Independent Roulette: the block's uniforms, off the steps' critical
+            // path; lane l computes step base + l, whose candidate r takes word
+            // r mod 4 of the Philox block at counter (step, ant, iteration,
+            // 1 + r / 4), and stores them at ir_words[l kw + r]
+            const int kw = ir_words_per_step(k);
+            for (int q = 0; q < kw / 4; ++q) {
+                const uint4 blk = philox_block((uint32_t)(base + lane), T.ant, T.iteration,
+                                               1u + (uint32_t)q, (uint32_t)T.seed,
+                                               (uint32_t)(T.seed >> 32));
+                *(uint4 *)&T.ir_words[lane * kw + 4 * q] = blk;
+            }
+        }
         // staged outputs: lane l holds step base + l (step 0 is the start city)
         int32_t st_city = start;
         uint32_t st_slot = kNoSlot;
@@ -343,6 +363,9 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
             const CandW e = hit ? eg : en;
             const int32_t j = e.city;
             const uint32_t seen = visited(j);          // every lane reads a valid word
+            // Independent Roulette: this step's uniform for candidate lr (read
+            // beside the visited word)
+            const uint32_t xw = kSampler != 0 ? T.ir_words[idx * ir_words_per_step(k) + lr] : 0u;
             const bool live = active && seen == 0u && e.w > 0.0f;
             // the same lanes as ballot(live), from single-compare ballots (no
             // lane mask re-materialised in a vector register)
@@ -362,11 +385,6 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
             if constexpr (kSampler != 0) {
                 // Independent Roulette: the largest product wins
                 if (any) {
-                    const uint4 blk = philox_block((uint32_t)step, T.ant, T.iteration,
-                                                   1u + (uint32_t)(lane >> 2), (uint32_t)T.seed,
-                                                   (uint32_t)(T.seed >> 32));
-                    const int wd = lane & 3;
-                    const uint32_t xw = wd == 0 ? blk.x : wd == 1 ? blk.y : wd == 2 ? blk.z : blk.w;
                     const double v = live ? wv * ((double)xw * 0x1p-32) : -1.0;
                     const double vmax = read_lane_f64(wave_incl_max_f64(v, KP), k - 1);
                     const uint64_t top = __builtin_amdgcn_ballot_w64(v == vmax) & any;

@@ -73,6 +73,8 @@ __global__ __launch_bounds__(kWave) void k_construct(ConstructArgs A)
     T.lbest = A.lbest ? A.lbest + (int64_t)a * A.n : nullptr;
     T.p_threshold = A.p_threshold;
     T.max_modify = A.max_modify;
+    if constexpr (kSampler != 0)   // the uniforms follow the visited set, 16-byte aligned
+        T.ir_words = vis + ((((int64_t)A.n + 31) / 32 * 4 + 15) & ~(int64_t)15) / 4;
     const int64_t len = build_ant_fixed<KP, kProb, PositionSpace, kSampler, true>(
         T, VisBits{vis}, [&]() { return grid_view(A.grid); });
     if (lane_id() == 0) A.lengths[a] = len;     // exact closed length
@@ -105,10 +107,12 @@ static int construct(const int32_t *xy, int32_t n, int32_t k, const int32_t *nn,
     const size_t need = aco_construct_workspace_bytes(n, k);
     if (ws_bytes < need)
         return fail(ACO_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
-    const size_t lds = bitmask_bytes(n);
+    size_t lds = bitmask_bytes(n);
+    if (sampler == ACO_SAMPLER_INDEPENDENT)   // plus one block of uniforms (64 steps)
+        lds = ((lds + 15) & ~(size_t)15) + (size_t)kWave * ir_words_per_step(k) * 4;
     if (lds > max_lds_per_block())
-        return fail(ACO_ERR_UNSUPPORTED, "visited bitmask of %zu bytes exceeds LDS (%zu)", lds,
-                    max_lds_per_block());
+        return fail(ACO_ERR_UNSUPPORTED, "visited set (and uniforms) of %zu bytes exceed LDS (%zu)",
+                    lds, max_lds_per_block());
     hipStream_t st = as_stream(stream);
     CandW *rows = (CandW *)ws;
     const GridLayout lay(n);
