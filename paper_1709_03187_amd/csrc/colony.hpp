@@ -373,11 +373,11 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
                                  __builtin_amdgcn_ballot_w64(e.w > 0.0f) & act_mask;
             // the first candidate that can be chosen is the likeliest next city
             // (rows are in distance order): its row is loaded while the scan runs
-            int32_t guess = -1;
-            if (any) {
-                guess = read_lane_i32(j, __ffsll((unsigned long long)any) - 1);
-                eg = T.rows[(int64_t)guess * k + lr];
-            }
+            // (issued without a branch: with no live candidate the row of lane
+            // 63's valid city is loaded and serves only if that city is taken)
+            const int32_t guess =
+                read_lane_i32(j, __builtin_ctzll((unsigned long long)(any | (1ull << 63))));
+            eg = T.rows[(int64_t)guess * k + lr];
             const double wv = live ? (double)e.w : 0.0;
             int32_t jn;
             uint32_t slot;
