@@ -112,6 +112,31 @@ def test_paper_method_partial_independent_local_best_pheromone():
         np.testing.assert_array_equal(_np(col.tau), tau)
 
 
+
+@pytest.mark.parametrize("n,k", [(300, 20), (257, 33), (401, 64), (150, 7)])
+def test_independent_roulette_wide_and_narrow_rows(n, k):
+    """Rows of 7 to 64 candidates (scan widths 8, 32 and 64; 2 to 16 Philox
+    blocks of uniforms per step staged in LDS), full and partial tours."""
+    import paper_1709_03187_amd as aco
+    xy = instances.uniform_coords(n, 40 + k)
+    m, seed, M, p = 8, 17, n // 3, 1.0
+    col = colony(xy, k=k, m=m, seed=seed)
+    col.setup()
+    nn, nnd = orc.knn_rows(xy, k, threads=threads())
+    tau = _np(col.tau).copy()
+    dummy = np.zeros((m, n), np.int32)
+    col.construct_ex(0, sampler=aco.ACO_SAMPLER_INDEPENDENT)
+    tours, lengths = _np(col.tours), _np(col.lengths)
+    tot = check_ir(xy, nn, nnd, tau, seed, 0, dummy, 0.0, 1, tours, lengths, _np(col.slots),
+                   range(m), f"ir n={n} k={k}")
+    col.update_local_best()
+    lbest, _ = orc.update_local_best(dummy, np.full(m, 2**63 - 1), tours, lengths)
+    col.construct_ex(1, sampler=aco.ACO_SAMPLER_INDEPENDENT, p_partial=p, max_modify=M,
+                     partial=True)
+    tot2 = check_ir(xy, nn, nnd, tau, seed, 1, lbest, p, M, _np(col.tours), _np(col.lengths),
+                    _np(col.slots), range(m), f"ir partial n={n} k={k}")
+    say(f"[ir] n={n} k={k}: full {tot}, partial {tot2}")
+
 def test_independent_roulette_full_size_sample():
     import paper_1709_03187_amd as aco
     cfg = instances.CONFIGS["c3"]
