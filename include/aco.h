@@ -287,7 +287,9 @@ int aco_construct_partial(const int32_t *xy, int32_t n, int32_t k, const int32_t
  *   lbest   NULL for full tours, else PartialACO with p_partial and
  *           max_modify as in aco_construct_partial.
  * opts is a host pointer (NULL: roulette, full tours).  Other arguments and
- * errors as aco_construct_tours. */
+ * errors as aco_construct_tours; Independent Roulette also keeps one block of
+ * uniforms in LDS (64 steps x k rounded up to 4 words), so UNSUPPORTED is
+ * returned when that and the visited bitmask together do not fit. */
 #define ACO_SAMPLER_ROULETTE 0
 #define ACO_SAMPLER_INDEPENDENT 1
 typedef struct aco_construct_opts {
