@@ -158,7 +158,8 @@ def batched_block():
             "ms_per_iteration": ms / iters, "setup_ms": t_setup * 1e3,
             "first_run_with_tuning_s": t_tuned_run,
             "tuned": {"waves_per_instance": tuned[0],
-                      "visited_layout": "bits" if tuned[1] == 1 else "bytes",
+                      "visited_layout": {1: "bits", 2: "bytes", 3: "bits"}[tuned[1]],
+                      "ants_per_wave": 4 if tuned[1] == 3 else 1,
                       "waves_per_simd": tuned[2]},
             "mean_best_len": float(L0.mean())}
 

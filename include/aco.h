@@ -211,7 +211,9 @@ int aco_run(const int32_t *xy, int32_t n, const aco_params_t *p, int32_t *best_t
  * runs iterations first .. first+count-1 of every instance in ONE persistent
  * kernel launch (no allocation, no host synchronisation: it can be captured in
  * a HIP graph); its iter_best is [B][count].  `waves` = waves per instance
- * workgroup (1, 2, 4, 8, 16), `vis_layout` = ACO_VIS_BITS / ACO_VIS_BYTES and
+ * workgroup (1, 2, 4, 8, 16), `vis_layout` = ACO_VIS_BITS / ACO_VIS_BYTES (one
+ * ant per wave, a bit or a byte per city) or ACO_VIS_BITS_X4 (four ants per
+ * wave on its four 16-lane rows, a bit per city each; k <= 16) and
  * `occupancy` = waves per SIMD the kernel's registers allow (4 or 8), each 0
  * for the tuned value, change the speed, never the results.  aco_run_batched
  * = set-up + all iterations; with autotune != 0 its first iterations each run
@@ -224,6 +226,7 @@ int aco_run(const int32_t *xy, int32_t n, const aco_params_t *p, int32_t *best_t
  * ------------------------------------------------------------------------ */
 #define ACO_VIS_BITS 1
 #define ACO_VIS_BYTES 2
+#define ACO_VIS_BITS_X4 3
 
 typedef struct aco_batch_layout {
     size_t nn, nnd, rev, eta_b, tau, tours, slots, lengths, total;

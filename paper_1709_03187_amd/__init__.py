@@ -49,6 +49,7 @@ ACO_MLP_OUT_LOGIT = 0
 ACO_MLP_OUT_ETA_B = 1
 ACO_VIS_BITS = 1
 ACO_VIS_BYTES = 2
+ACO_VIS_BITS_X4 = 3
 
 
 class AcoError(RuntimeError):

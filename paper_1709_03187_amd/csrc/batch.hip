@@ -270,7 +270,8 @@ struct ColonyParams {
     int32_t shift;
     uint64_t seed;
     int32_t first_iteration, count;
-    size_t vis_stride;   // LDS bytes per wave for the visited set
+    size_t vis_stride;   // LDS bytes per wave for the visited set(s)
+    size_t set_bytes;    // four ants per wave: bytes of one ant's visited bitmask
     int32_t *best_tours; // [N]
     int64_t *best_lens;  // [B]
     int64_t *iter_best;  // row b at iter_best + b * ib_stride, or nullptr
@@ -296,8 +297,9 @@ __device__ __forceinline__ int64_t wave_min_i64_shfl(int64_t v)
 
 // OCC = waves per SIMD the register allocation must allow (4: up to 128
 // VGPRs; 8: 64 VGPRs, spilling on the rare fallback path): the ants resident
-// per CU, one of the tuned knobs.
-template <int KP, class Vis, int OCC>
+// per CU, one of the tuned knobs.  APW = ants per wave: 1 (build_ant) or 4
+// (build_ants4, k <= 16, bit visited sets); the tours are the same.
+template <int KP, class Vis, int OCC, int APW>
 __global__ __launch_bounds__(1024, OCC) void k_b_colony(BatchState S, ColonyParams P)
 {
     extern __shared__ __align__(16) unsigned char lds[];
@@ -324,7 +326,28 @@ __global__ __launch_bounds__(1024, OCC) void k_b_colony(BatchState S, ColonyPara
 
     for (int it = 0; it < P.count; ++it) {
         const uint32_t t = (uint32_t)(P.first_iteration + it);
-        // 1. construction: ant a on wave a mod W
+        // 1. construction: ant a on wave a mod W (four at a time: a, a + W,
+        //    a + 2W, a + 3W on one wave)
+        if constexpr (APW == 4) {
+            unsigned char *mine = lds + (size_t)wave * P.vis_stride;
+            for (int a0 = wave; a0 < m; a0 += 4 * W) {
+                Ants4Task T4;
+                T4.xy = xy;
+                T4.rows = rows;
+                T4.n = n;
+                T4.k = k;
+                T4.ant0 = (uint32_t)a0;
+                T4.ant_stride = (uint32_t)W;
+                int nv = 1;
+                while (nv < 4 && a0 + nv * W < m) ++nv;
+                T4.nvalid = nv;
+                T4.iteration = t;
+                T4.seed = P.seed;
+                T4.tours = tours;
+                T4.slots = slots;
+                build_ants4(T4, mine, P.set_bytes, [&]() { return batch_grid(S, b); });
+            }
+        } else
         for (int a = wave; a < m; a += W) {
             AntTask T;
             T.xy = xy;
@@ -528,19 +551,30 @@ using ColonyKernel = void (*)(BatchState, ColonyParams);
 template <class Vis, int OCC>
 static ColonyKernel colony_kernel_k(int k)
 {
-    return k <= 8 ? k_b_colony<8, Vis, OCC> : k <= 16 ? k_b_colony<16, Vis, OCC>
-           : k <= 32 ? k_b_colony<32, Vis, OCC> : k_b_colony<64, Vis, OCC>;
+    return k <= 8 ? k_b_colony<8, Vis, OCC, 1> : k <= 16 ? k_b_colony<16, Vis, OCC, 1>
+           : k <= 32 ? k_b_colony<32, Vis, OCC, 1> : k_b_colony<64, Vis, OCC, 1>;
 }
 
 static ColonyKernel colony_kernel(int k, int layout, int occ)
 {
+    if (layout == ACO_VIS_BITS_X4)   // k <= 16 (checked by the callers)
+        return occ == 8 ? (k <= 8 ? k_b_colony<8, VisBits, 8, 4> : k_b_colony<16, VisBits, 8, 4>)
+                        : (k <= 8 ? k_b_colony<8, VisBits, 4, 4> : k_b_colony<16, VisBits, 4, 4>);
     if (layout == ACO_VIS_BYTES)
         return occ == 8 ? colony_kernel_k<VisBytes, 8>(k) : colony_kernel_k<VisBytes, 4>(k);
     return occ == 8 ? colony_kernel_k<VisBits, 8>(k) : colony_kernel_k<VisBits, 4>(k);
 }
 
+// Bytes of one ant's bit visited set, padded to 16.
+static size_t set_bytes_bits(int64_t nmax)
+{
+    return ((size_t)((nmax + 31) / 32) * 4 + 15) & ~(size_t)15;
+}
+
 static size_t vis_stride(int layout, int64_t nmax)
 {
+    if (layout == ACO_VIS_BITS_X4)
+        return (ants4_lds_bytes(set_bytes_bits(nmax)) + 15) & ~(size_t)15;
     const size_t b = layout == ACO_VIS_BYTES ? (size_t)((nmax + 3) & ~3) : (size_t)((nmax + 31) / 32) * 4;
     return (b + 15) & ~(size_t)15;
 }
@@ -583,6 +617,7 @@ static int launch_colony(const BatchState &S0, const BatchLayoutHost &L, const a
     P.first_iteration = first;
     P.count = count;
     P.vis_stride = vis_stride(layout, L.nmax);
+    P.set_bytes = set_bytes_bits(L.nmax);
     P.best_tours = best_tours;
     P.best_lens = best_lens;
     P.iter_best = iter_best;
@@ -680,8 +715,11 @@ extern "C" int aco_batch_iterate(const int32_t *xy, const int64_t *offsets, int3
     ACO_REQUIRE(first_iteration >= 0 && count >= 0, "bad iteration range");
     ACO_REQUIRE(waves == 0 || waves == 1 || waves == 2 || waves == 4 || waves == 8 || waves == 16,
                 "waves per instance must be 0 (tuned), 1, 2, 4, 8 or 16");
-    ACO_REQUIRE(vis_layout == 0 || vis_layout == ACO_VIS_BITS || vis_layout == ACO_VIS_BYTES,
+    ACO_REQUIRE(vis_layout == 0 || vis_layout == ACO_VIS_BITS || vis_layout == ACO_VIS_BYTES ||
+                    vis_layout == ACO_VIS_BITS_X4,
                 "bad visited-set layout");
+    ACO_REQUIRE(vis_layout != ACO_VIS_BITS_X4 || p->k <= 16,
+                "four ants per wave need k <= 16 (k = %d)", p->k);
     ACO_REQUIRE(occupancy == 0 || occupancy == 4 || occupancy == 8,
                 "occupancy must be 0 (tuned), 4 or 8 waves per SIMD");
     BatchLayoutHost L;
@@ -733,11 +771,14 @@ extern "C" int aco_run_batched(const int32_t *xy, const int64_t *offsets, int32_
     if (autotune) {
         // every candidate runs one real iteration (results do not depend on
         // the configuration); the fastest runs the rest
-        const Tuning cand[] = {{4, ACO_VIS_BITS, 4},   {8, ACO_VIS_BITS, 4},
-                               {16, ACO_VIS_BITS, 4},  {4, ACO_VIS_BYTES, 4},
-                               {8, ACO_VIS_BYTES, 4},  {16, ACO_VIS_BYTES, 4},
-                               {4, ACO_VIS_BITS, 8},   {8, ACO_VIS_BITS, 8},
-                               {16, ACO_VIS_BITS, 8},  {8, ACO_VIS_BYTES, 8}};
+        const Tuning cand[] = {{4, ACO_VIS_BITS, 4},     {8, ACO_VIS_BITS, 4},
+                               {16, ACO_VIS_BITS, 4},    {4, ACO_VIS_BYTES, 4},
+                               {8, ACO_VIS_BYTES, 4},    {16, ACO_VIS_BYTES, 4},
+                               {4, ACO_VIS_BITS, 8},     {8, ACO_VIS_BITS, 8},
+                               {16, ACO_VIS_BITS, 8},    {8, ACO_VIS_BYTES, 8},
+                               {4, ACO_VIS_BITS_X4, 4},  {8, ACO_VIS_BITS_X4, 4},
+                               {16, ACO_VIS_BITS_X4, 4}, {4, ACO_VIS_BITS_X4, 8},
+                               {8, ACO_VIS_BITS_X4, 8},  {16, ACO_VIS_BITS_X4, 8}};
         hipEvent_t e0, e1;
         ACO_HIP_CHECK(hipEventCreate(&e0));
         ACO_HIP_CHECK(hipEventCreate(&e1));
@@ -745,6 +786,7 @@ extern "C" int aco_run_batched(const int32_t *xy, const int64_t *offsets, int32_
         for (const Tuning &c : cand) {
             if (it >= p->iterations) break;
             if (colony_lds(c.waves, c.layout, L.nmax, p->m) > max_lds_per_block()) continue;
+            if (c.layout == ACO_VIS_BITS_X4 && p->k > 16) continue;
             ACO_HIP_CHECK(hipEventRecord(e0, st));
             rc = launch_colony(S, L, p, it, 1, c, best_tours, best_lens,
                                iter_best ? iter_best + it : nullptr, p->iterations, st);

@@ -61,7 +61,9 @@ def inst(S, off, b, m=M):
                 best_len=int(S["best_lens"][b]))
 
 
-def test_batch_setup_and_iterations_match_oracle():
+@pytest.mark.parametrize("layout", [1, 3])
+def test_batch_setup_and_iterations_match_oracle(layout):
+    """layout 1: one ant per wave; 3: four ants per wave (one per 16-lane row)."""
     import torch
     # 20 instances of the batched workload plus the smallest legal size (n = k + 1)
     tiny = instances.uniform_coords(K + 1, 99)
@@ -89,7 +91,7 @@ def test_batch_setup_and_iterations_match_oracle():
     for t in range(3):
         say(f"[batch] iteration {t}")
         ib = torch.empty((bt.B, 1), dtype=torch.int64, device="cuda")
-        bt.iterate(t, 1, waves=8, layout=1, iter_best=ib)
+        bt.iterate(t, 1, waves=8, layout=layout, iter_best=ib)
         S = state(bt)
         ibn = ib.cpu().numpy()[:, 0]
         for b in range(bt.B):
@@ -109,7 +111,8 @@ def test_batch_setup_and_iterations_match_oracle():
 
 
 CONFIGS = [(1, 1, 4), (2, 1, 4), (4, 1, 4), (8, 1, 4), (16, 1, 4), (4, 2, 4), (8, 2, 4),
-           (16, 2, 4), (4, 1, 8), (16, 1, 8), (8, 2, 8)]
+           (16, 2, 4), (4, 1, 8), (16, 1, 8), (8, 2, 8), (1, 3, 4), (4, 3, 4), (16, 3, 4),
+           (2, 3, 8), (8, 3, 8), (16, 3, 8)]
 
 
 def test_batch_invariance_across_configurations():
@@ -128,12 +131,40 @@ def test_batch_invariance_across_configurations():
             np.testing.assert_array_equal(a, b)
 
 
+@pytest.mark.parametrize("m,k", [(10, 12), (7, 8), (13, 16)])
+def test_batch_four_ants_per_wave_partial_groups(m, k):
+    """Ant counts that leave some of a wave's four rows empty, and k = 8, 12, 16:
+    four ants per wave give the same state as one ant per wave."""
+    import torch
+    results = []
+    for waves, layout in ((4, 1), (4, 3), (2, 3), (1, 3)):
+        bt, xy, off, sizes = make_batch(12, k=k, m=m)
+        bt.setup()
+        ib = torch.empty((bt.B, 3), dtype=torch.int64, device="cuda")
+        bt.iterate(0, 3, waves=waves, layout=layout, iter_best=ib, occupancy=4)
+        S = state(bt)
+        results.append((S["tau"], S["best_lens"], S["best_tours"], S["tours"], S["slots"],
+                        S["lengths"], ib.cpu().numpy()))
+    for r in results[1:]:
+        for a, b in zip(results[0], r):
+            np.testing.assert_array_equal(a, b)
+
+
+def test_batch_four_ants_rejects_wide_rows():
+    import paper_1709_03187_amd as aco
+    bt, xy, off, sizes = make_batch(4, k=20, m=8)
+    bt.setup()
+    with pytest.raises(aco.AcoError) as e:
+        bt.iterate(0, 1, waves=4, layout=aco.ACO_VIS_BITS_X4)
+    assert e.value.code == aco.ACO_ERR_INVALID_ARG
+
+
 def test_batch_autotuned_run_equals_fixed_configuration():
     import torch
     bt, xy, off, sizes = make_batch(40, iterations=9)
     ib = torch.empty((bt.B, 9), dtype=torch.int64, device="cuda")
     tuned = bt.run(autotune=1, iter_best=ib)
-    assert tuned[0] in (4, 8, 16) and tuned[1] in (1, 2) and tuned[2] in (4, 8)
+    assert tuned[0] in (4, 8, 16) and tuned[1] in (1, 2, 3) and tuned[2] in (4, 8)
     A = state(bt)
     bt2, *_ = make_batch(40, iterations=9)
     bt2.setup()
