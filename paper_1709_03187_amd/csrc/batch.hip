@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "colony.hpp"
+#include "colony_x4.hpp"
 #include "common.hpp"
 
 namespace aco {
