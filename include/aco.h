@@ -215,7 +215,9 @@ int aco_run(const int32_t *xy, int32_t n, const aco_params_t *p, int32_t *best_t
  * ant per wave, a bit or a byte per city) or ACO_VIS_BITS_X4 (four ants per
  * wave on its four 16-lane rows, a bit per city each; k <= 16) and
  * `occupancy` = waves per SIMD the kernel's registers allow (4 or 8), each 0
- * for the tuned value, change the speed, never the results.  aco_run_batched
+ * for the tuned value (before tuning: four ants per wave with the most waves
+ * the LDS holds when k <= 16, else 8 waves, bits, 4 per SIMD), change the
+ * speed, never the results.  aco_run_batched
  * = set-up + all iterations; with autotune != 0 its first iterations each run
  * a different configuration, timed, and the fastest (cached per device and
  * shape) runs the rest; tuned_out (host int32 [3], may be NULL) receives

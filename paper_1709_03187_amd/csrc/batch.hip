@@ -591,6 +591,17 @@ struct Tuning {
     int waves, layout, occ;
 };
 
+// The shape used before (or without) tuning: four ants per wave with as many
+// waves per instance as the LDS holds when k <= 16, else one ant per wave.
+static Tuning default_tuning(int k, int64_t nmax, int m)
+{
+    if (k <= 16)
+        for (int w : {16, 8, 4})
+            if (colony_lds(w, ACO_VIS_BITS_X4, nmax, m) <= max_lds_per_block())
+                return Tuning{w, ACO_VIS_BITS_X4, 8};
+    return Tuning{8, ACO_VIS_BITS, 4};
+}
+
 // Tuned configuration per (device, k, m, largest n, batch size).
 static std::mutex g_tune_mu;
 static std::map<std::tuple<int, int, int, int64_t, int>, Tuning> g_tuned;
@@ -730,7 +741,7 @@ extern "C" int aco_batch_iterate(const int32_t *xy, const int64_t *offsets, int3
     if (count == 0) return ACO_OK;
     int dev = 0;
     (void)hipGetDevice(&dev);
-    Tuning cfg{8, ACO_VIS_BITS, 4};
+    Tuning cfg = default_tuning(p->k, L.nmax, p->m);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tuned.find(std::make_tuple(dev, p->k, p->m, L.nmax, B));
@@ -739,6 +750,11 @@ extern "C" int aco_batch_iterate(const int32_t *xy, const int64_t *offsets, int3
     if (waves) cfg.waves = waves;
     if (vis_layout) cfg.layout = vis_layout;
     if (occupancy) cfg.occ = occupancy;
+    // a given wave count with the default four-ant layout may not fit in LDS:
+    // then one ant per wave
+    if (!vis_layout && cfg.layout == ACO_VIS_BITS_X4 &&
+        colony_lds(cfg.waves, cfg.layout, L.nmax, p->m) > max_lds_per_block())
+        cfg.layout = ACO_VIS_BITS;
     BatchState S = batch_state(ws, L, xy, B, p->k, p->m);
     return launch_colony(S, L, p, first_iteration, count, cfg, best_tours, best_lens, iter_best,
                          count, as_stream(stream));
@@ -759,7 +775,7 @@ extern "C" int aco_run_batched(const int32_t *xy, const int64_t *offsets, int32_
     int dev = 0;
     (void)hipGetDevice(&dev);
     const auto key = std::make_tuple(dev, p->k, p->m, L.nmax, B);
-    Tuning best{8, ACO_VIS_BITS, 4};
+    Tuning best = default_tuning(p->k, L.nmax, p->m);
     int32_t it = 0;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
