@@ -24,8 +24,13 @@ def edge_instances():
     tiny = instances.uniform_coords(3, 2)
     k64 = instances.uniform_coords(65, 3)
     neg = instances.uniform_coords(400, 4, hi=2 * 10**8) - 10**8
+    # rows that are not a power of two wide: scan widths 8, 32 and 64
+    k7 = instances.uniform_coords(333, 5)
+    k20 = instances.uniform_coords(517, 6)
+    k33 = instances.uniform_coords(301, 7)
     return {"line": (line, 6), "ties": (ties, 12), "clustered": (clus, 16), "n3": (tiny, 2),
-            "k64": (k64, 64), "negative": (neg, 10)}
+            "k64": (k64, 64), "negative": (neg, 10), "k7": (k7, 7), "k20": (k20, 20),
+            "k33": (k33, 33)}
 
 
 CASES = {"c1": (instances.make_coords("c1"), 10), **edge_instances()}
@@ -117,7 +122,8 @@ def test_parameter_variants(alpha, beta, rho, shift):
                   label=f"a{alpha} b{beta} r{rho} s{shift}")
 
 
-@pytest.mark.parametrize("name", ["ties", "clustered", "line", "n3", "k64", "negative"])
+@pytest.mark.parametrize("name", ["ties", "clustered", "line", "n3", "k64", "negative", "k7",
+                                  "k20", "k33"])
 def test_edge_cases_run(name):
     xy, k = CASES[name]
     run_and_check(xy, k, 8, 1.0, 2.0, 0.1, 2, 5, tau_noise=True, label=name)
