@@ -23,6 +23,15 @@ int fail(int code, const char *fmt, ...)
 
 void clear_error() { g_last_error[0] = '\0'; }
 
+int num_cus()
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 1;
+    return v > 0 ? v : 1;
+}
+
 size_t max_lds_per_block()
 {
     int dev = 0, v = 0;

@@ -18,6 +18,8 @@ void clear_error();
 
 // Largest dynamic LDS allocation one workgroup may request on the current device.
 size_t max_lds_per_block();
+// Compute units of the current device.
+int num_cus();
 
 inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
