@@ -143,14 +143,15 @@ static int construct(const int32_t *xy, int32_t n, int32_t k, const int32_t *nn,
     else
         kern = k <= 8 ? k_construct<8, 0, false> : k <= 16 ? k_construct<16, 0, false>
              : k <= 32 ? k_construct<32, 0, false> : k_construct<64, 0, false>;
-    // four ants per workgroup when their slices fit; when the launch needs no
-    // more workgroups than there are CUs, the request is padded past half the
-    // LDS so that each CU takes one workgroup (four ants on its four SIMDs)
+    // up to four ants per CU (one per SIMD): one workgroup of four ants per CU,
+    // the LDS request padded past half the CU's so that no CU takes two; more
+    // ants than that (or slices too large for four): one ant per workgroup, as
+    // many resident as the LDS allows
     const size_t lmax = max_lds_per_block();
-    const int wpb = 4 * lds <= lmax ? 4 : 2 * lds <= lmax ? 2 : 1;
+    const int wpb = ((int64_t)m <= 4 * (int64_t)num_cus() && 4 * lds <= lmax) ? 4 : 1;
     const int32_t blocks = (m + wpb - 1) / wpb;
     size_t lds_req = (size_t)wpb * lds;
-    if (blocks <= num_cus() && lds_req <= lmax / 2) lds_req = lmax / 2 + 16;
+    if (wpb == 4 && lds_req <= lmax / 2) lds_req = lmax / 2 + 16;
     if (lds_req > 65536)
         ACO_HIP_CHECK(hipFuncSetAttribute((const void *)kern,
                                           hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -226,6 +226,26 @@ def test_ant_split_and_determinism():
     np.testing.assert_array_equal(a[7:], b2)
 
 
+def test_one_and_four_ants_per_workgroup_agree():
+    """More ants than four per CU run one per workgroup; the same ants launched
+    four per workgroup draw the same tours."""
+    import torch
+    xy = instances.uniform_coords(300, 9)
+    m = 1100
+    col = colony(xy, k=8, m=m)
+    col.setup()
+    col.construct(2)
+    torch.cuda.synchronize()
+    many = to_np(col.tours).copy()
+    assert (np.sort(many, axis=1) == np.arange(300)).all()
+    col.construct(2, m=97, ant0=1003)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(to_np(col.tours)[:97], many[1003:1100])
+    col.construct(2, m=5, ant0=0)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(to_np(col.tours)[:5], many[:5])
+
+
 def test_sampling_distribution_tiny():
     """GPU tour frequencies on a 5-city instance against the exact distribution."""
     import math
