@@ -291,6 +291,11 @@ int aco_construct_partial(const int32_t *xy, int32_t n, int32_t k, const int32_t
  *           computed: step_prob must be NULL.
  *   lbest   NULL for full tours, else PartialACO with p_partial and
  *           max_modify as in aco_construct_partial.
+ *   lbest_len  NULL, or device int64 [m] with the exact closed length of
+ *           every local best (as aco_update_local_best keeps it): the kept
+ *           part's length is then that length minus the edges outside the
+ *           kept part, instead of a sum over the kept part (same result when
+ *           the lengths are exact; a wrong length gives a wrong tour length).
  * opts is a host pointer (NULL: roulette, full tours).  Other arguments and
  * errors as aco_construct_tours; Independent Roulette also keeps one block of
  * uniforms in LDS (64 steps x k rounded up to 4 words), so UNSUPPORTED is
@@ -302,6 +307,7 @@ typedef struct aco_construct_opts {
     double p_partial;
     int32_t max_modify;
     const int32_t *lbest;
+    const int64_t *lbest_len;   /* [m] or NULL (see above) */
 } aco_construct_opts_t;
 
 int aco_construct_ex(const int32_t *xy, int32_t n, int32_t k, const int32_t *nn,

@@ -66,7 +66,7 @@ class AcoParams(C.Structure):
 
 class AcoConstructOpts(C.Structure):
     _fields_ = [("sampler", C.c_int32), ("p_partial", C.c_double), ("max_modify", C.c_int32),
-                ("lbest", C.c_void_p)]
+                ("lbest", C.c_void_p), ("lbest_len", C.c_void_p)]
 
 
 class AcoTwoOptStats(C.Structure):
@@ -269,10 +269,12 @@ def aco_construct_partial(xy, n, k, nn, nnd, eta_b, grid, tau, m, ant0, alpha, s
 
 def aco_construct_ex(xy, n, k, nn, nnd, eta_b, grid, tau, m, ant0, alpha, seed, iteration, sampler,
                      p_partial, max_modify, lbest, tours, lengths, slots, step_prob, ws,
-                     stream=None):
+                     stream=None, lbest_len=None):
     torch = _t()
     opts = AcoConstructOpts(int(sampler), float(p_partial), int(max_modify),
-                            None if lbest is None else _ptr(lbest, torch.int32, "lbest").value)
+                            None if lbest is None else _ptr(lbest, torch.int32, "lbest").value,
+                            None if lbest_len is None
+                            else _ptr(lbest_len, torch.int64, "lbest_len").value)
     _check(lib().aco_construct_ex(
         _ptr(xy, torch.int32, "xy"), n, k, _ptr(nn, torch.int32, "nn"),
         _ptr(nnd, torch.int32, "nnd"), _ptr(eta_b, torch.float32, "eta_b"),
@@ -457,14 +459,16 @@ class Colony:
                               self.step_prob, self.cws, stream)
 
     def construct_ex(self, iteration, sampler=ACO_SAMPLER_ROULETTE, p_partial=0.0, max_modify=1,
-                     partial=False, stream=None):
-        """Construction with a chosen sampler; partial=True rebuilds from the local bests."""
+                     partial=False, stream=None, use_lbest_len=True):
+        """Construction with a chosen sampler; partial=True rebuilds from the local bests
+        (whose kept part's length then comes from their lengths, unless
+        use_lbest_len is False)."""
         aco_construct_ex(self.xy, self.n, self.k, self.nn, self.nnd, self.eta_b, self.grid,
                          self.tau, self.m, 0, self.alpha, self.seed, iteration, sampler,
                          p_partial, max_modify, self.lbest if partial else None, self.tours,
                          self.lengths, self.slots,
                          self.step_prob if sampler == ACO_SAMPLER_ROULETTE else None, self.cws,
-                         stream)
+                         stream, lbest_len=self.lbest_len if partial and use_lbest_len else None)
 
     def update_local_best(self, stream=None):
         """Take this iteration's tours into the local bests where strictly shorter

@@ -180,6 +180,7 @@ struct AntTask {
     // indices) or nullptr for a full construction; the partial-modification
     // threshold P = round(p 2^32) and the cap M on the rebuilt cities.
     const int32_t *lbest = nullptr;
+    const int64_t *lbest_len = nullptr;   // this ant's local best length, or nullptr
     uint64_t p_threshold = 0;
     int32_t max_modify = 0;
     // Independent Roulette only: LDS for one block's uniforms, 64 steps x
@@ -273,7 +274,7 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
                     if constexpr (kProb) T.prob[t] = 1.0f;
                 }
             }
-            if constexpr (kLen) {
+            if (kLen && !T.lbest_len) {
                 int2 pc[kU];
 #pragma unroll
                 for (int u = 0; u < kU; ++u) {
@@ -290,6 +291,20 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
                     kprev.x = __builtin_amdgcn_readlane(pc[u].x, kWave - 1);
                     kprev.y = __builtin_amdgcn_readlane(pc[u].y, kWave - 1);
                 }
+            }
+        }
+        if (kLen && T.lbest_len) {
+            // the kept part's internal edges: the local best's length minus its
+            // n - keep + 1 edges from the last kept city round to the first
+            if (lane == 0) part += *T.lbest_len;
+            for (int32_t u = lane; u <= n - keep; u += kWave) {
+                int64_t q0 = s_pos + keep - 1 + u;   // < 2n - 1
+                q0 -= q0 >= n ? n : 0;
+                const int64_t q1 = q0 + 1 == n ? 0 : q0 + 1;
+                const int32_t c0 = T.lbest[q0], c1 = T.lbest[q1];
+                const int2 p0 = ((const int2 *)T.xy)[(uint32_t)c0 < (uint32_t)n ? c0 : 0];
+                const int2 p1 = ((const int2 *)T.xy)[(uint32_t)c1 < (uint32_t)n ? c1 : 0];
+                part -= nint_sqrt(sq_dist(p0.x, p0.y, p1.x, p1.y));
             }
         }
         const int32_t last_kept = T.lbest[(s_pos + keep - 1) % n];

@@ -47,6 +47,7 @@ struct ConstructArgs {
     uint8_t *slots;
     float *step_prob;
     const int32_t *lbest;   // [m][n] local best tours (PartialACO) or nullptr
+    const int64_t *lbest_len;   // [m] their exact lengths, or nullptr
     uint64_t p_threshold;
     int32_t max_modify;
     int32_t m;              // ants in this launch
@@ -82,6 +83,7 @@ __global__ __launch_bounds__(4 * kWave) void k_construct(ConstructArgs A)
     T.slots = A.slots + (int64_t)a * A.n;
     T.prob = A.step_prob ? A.step_prob + (int64_t)a * A.n : nullptr;
     T.lbest = A.lbest ? A.lbest + (int64_t)a * A.n : nullptr;
+    T.lbest_len = A.lbest && A.lbest_len ? A.lbest_len + a : nullptr;
     T.p_threshold = A.p_threshold;
     T.max_modify = A.max_modify;
     if constexpr (kSampler != 0)   // the uniforms follow the visited set, 16-byte aligned
@@ -104,9 +106,9 @@ extern "C" size_t aco_construct_workspace_bytes(int32_t n, int32_t k)
 static int construct(const int32_t *xy, int32_t n, int32_t k, const int32_t *nn,
                      const int32_t *nnd, const float *eta_b, const void *grid, const float *tau,
                      int32_t m, int32_t ant0, double alpha, uint64_t seed, int64_t iteration,
-                     const int32_t *lbest, uint64_t p_threshold, int32_t max_modify,
-                     int32_t sampler, int32_t *tours, int64_t *lengths, uint8_t *slots,
-                     float *step_prob, void *ws, size_t ws_bytes, void *stream)
+                     const int32_t *lbest, const int64_t *lbest_len, uint64_t p_threshold,
+                     int32_t max_modify, int32_t sampler, int32_t *tours, int64_t *lengths,
+                     uint8_t *slots, float *step_prob, void *ws, size_t ws_bytes, void *stream)
 {
     ACO_REQUIRE(n >= 3 && n <= (1 << 27), "n = %d out of range [3, 2^27]", n);
     ACO_REQUIRE(k >= 1 && k <= ACO_MAX_K && k <= n - 1, "k = %d out of range", k);
@@ -158,7 +160,7 @@ static int construct(const int32_t *xy, int32_t n, int32_t k, const int32_t *nn,
                                           (int)lds_req));
     ConstructArgs A{xy,    rows,    grid,      n,     k,           ant0,
                     (uint32_t)iteration,       seed,      tours, lengths, slots,
-                    step_prob, lbest,   p_threshold, max_modify, m, (int32_t)lds};
+                    step_prob, lbest,   lbest_len, p_threshold, max_modify, m, (int32_t)lds};
     kern<<<blocks, wpb * kWave, lds_req, st>>>(A);
     ACO_LAUNCH_CHECK("k_construct");
     return ACO_OK;
@@ -173,8 +175,8 @@ extern "C" int aco_construct_tours(const int32_t *xy, int32_t n, int32_t k, cons
 {
     clear_error();
     return construct(xy, n, k, nn, nnd, eta_b, grid, tau, m, ant0, alpha, seed, iteration,
-                     nullptr, 0, 0, ACO_SAMPLER_ROULETTE, tours, lengths, slots, step_prob, ws,
-                     ws_bytes, stream);
+                     nullptr, nullptr, 0, 0, ACO_SAMPLER_ROULETTE, tours, lengths, slots,
+                     step_prob, ws, ws_bytes, stream);
 }
 
 extern "C" int aco_construct_partial(const int32_t *xy, int32_t n, int32_t k, const int32_t *nn,
@@ -193,8 +195,8 @@ extern "C" int aco_construct_partial(const int32_t *xy, int32_t n, int32_t k, co
     // P = round(p 2^32), ties to even (the current rounding mode)
     const uint64_t thr = (uint64_t)std::nearbyint(std::ldexp(p_partial, 32));
     return construct(xy, n, k, nn, nnd, eta_b, grid, tau, m, ant0, alpha, seed, iteration, lbest,
-                     thr, max_modify, ACO_SAMPLER_ROULETTE, tours, lengths, slots, step_prob, ws,
-                     ws_bytes, stream);
+                     nullptr, thr, max_modify, ACO_SAMPLER_ROULETTE, tours, lengths, slots,
+                     step_prob, ws, ws_bytes, stream);
 }
 
 extern "C" int aco_construct_ex(const int32_t *xy, int32_t n, int32_t k, const int32_t *nn,
@@ -205,7 +207,7 @@ extern "C" int aco_construct_ex(const int32_t *xy, int32_t n, int32_t k, const i
                                 float *step_prob, void *ws, size_t ws_bytes, void *stream)
 {
     clear_error();
-    aco_construct_opts_t o{ACO_SAMPLER_ROULETTE, 0.0, 0, nullptr};
+    aco_construct_opts_t o{ACO_SAMPLER_ROULETTE, 0.0, 0, nullptr, nullptr};
     if (opts) o = *opts;
     ACO_REQUIRE(o.sampler == ACO_SAMPLER_ROULETTE || o.sampler == ACO_SAMPLER_INDEPENDENT,
                 "sampler = %d unknown", o.sampler);
@@ -219,6 +221,6 @@ extern "C" int aco_construct_ex(const int32_t *xy, int32_t n, int32_t k, const i
         thr = (uint64_t)std::nearbyint(std::ldexp(o.p_partial, 32));
     }
     return construct(xy, n, k, nn, nnd, eta_b, grid, tau, m, ant0, alpha, seed, iteration,
-                     o.lbest, thr, o.max_modify, o.sampler, tours, lengths, slots, step_prob, ws,
-                     ws_bytes, stream);
+                     o.lbest, o.lbest_len, thr, o.max_modify, o.sampler, tours, lengths, slots,
+                     step_prob, ws, ws_bytes, stream);
 }

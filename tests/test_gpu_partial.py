@@ -212,3 +212,35 @@ def test_partial_with_local_best_pheromone():
         col.pheromone_from_local_best(base, delta)
         tau, q = orc.pheromone_local_best(nn, lbest, lbest_len, base, delta)
         np.testing.assert_array_equal(_np(col.tau), tau, err_msg=f"it={it}")
+
+
+@pytest.mark.parametrize("name,M,p", [("c1", 150, 0.95), ("c1", 999, 1.0), ("c1", 1, 1.0),
+                                      ("clustered", 40, 0.7)])
+def test_kept_length_from_local_best_lengths(name, M, p):
+    """The kept part's length taken from the local best's length (minus the
+    edges outside the kept part) equals the sum over the kept part; tours are
+    replayed by the oracle, lengths compared exactly."""
+    import torch
+    xy = instances.make_coords("c1") if name == "c1" else \
+        instances.clustered_coords(3000, 8, clusters=5, sigma=3e3)
+    k, m, seed = 10, 32, 12
+    col = colony(xy, k=k, m=m, seed=seed, want_prob=True)
+    col.setup()
+    nn, nnd = orc.knn_rows(xy, k, threads=threads())
+    tau = _np(col.tau).copy()
+    col.construct(0)
+    col.update_local_best()
+    for it in range(1, 4):
+        lbest = _np(col.lbest).copy()
+        col.construct_ex(it, p_partial=p, max_modify=M, partial=True, use_lbest_len=False)
+        ref = (_np(col.tours).copy(), _np(col.lengths).copy(), _np(col.slots).copy())
+        col.construct_ex(it, p_partial=p, max_modify=M, partial=True, use_lbest_len=True)
+        tours, lengths = _np(col.tours), _np(col.lengths)
+        np.testing.assert_array_equal(tours, ref[0])
+        np.testing.assert_array_equal(lengths, ref[1])
+        np.testing.assert_array_equal(_np(col.slots), ref[2])
+        check_partial(xy, nn, nnd, tau, seed, it, lbest, p, M, tours, lengths, _np(col.slots),
+                      _np(col.step_prob), range(0, m, 5), f"lbest_len {name} it={it}")
+        say(f"[partial] kept length from local best lengths: {name} M={M} it={it}")
+        col.update_local_best()
+        torch.cuda.synchronize()
