@@ -35,6 +35,8 @@ PINS = {
     "rev": "numpy search of the transposed lists",
     "philox4x32_10": "rocRAND's philox4x32_10 ten_rounds (library routine, compiled from its header)",
     "nearest_unvisited": "plain argmin of (nint d, j) and numpy brute force",
+    "nearest_unvisited_sweep": "the brute-force argmin on random visited sets (ties, duplicates, "
+                               "equal x, negative coordinates, the clustered 200K instance)",
     "nn_tour": "plain O(n^2) argmin walk",
     "construct/replay": "exact rational probabilities (fractions); exhaustive tour enumeration (n<=7); "
                         "uniform permutations for alpha=beta=0, k=n-1; invariants",
@@ -80,10 +82,11 @@ def lib():
             "oracle_tau0": (C.c_float, [i64, i64]),
             "oracle_construct": (None, [i64, C.c_int, p, p, p, p, p, dbl, dbl, u64, i64, p, i64,
                                         p, p, p, p, p, C.c_int]),
+            "oracle_nearest_unvisited_sweep": (i64, [p, i64, i64, p, p, p]),
             "oracle_replay": (None, [i64, C.c_int, p, p, p, p, p, dbl, dbl, u64, i64, i64, p, dbl,
-                                     p, p]),
-            "oracle_deposit": (None, [i64, C.c_int, p, i64, p, p, C.c_int, p]),
-            "oracle_update": (None, [i64, C.c_int, p, p, i64, p, p, dbl, C.c_int]),
+                                     p, p, p, p]),
+            "oracle_deposit": (None, [i64, C.c_int, p, i64, p, p, C.c_int, p, C.c_int]),
+            "oracle_update": (None, [i64, C.c_int, p, p, i64, p, p, dbl, C.c_int, C.c_int]),
             "oracle_run": (C.c_int, [i64, C.c_int, p, i64, dbl, dbl, dbl, i64, u64, C.c_int,
                                      C.c_int, p, p, p, p]),
             "oracle_partial_plan": (None, [u64, i64, i64, i64, u64, i64, p, p, p]),
@@ -185,6 +188,25 @@ def nearest_unvisited(xy, c: int, visited, plain: bool = False) -> int:
     return int(f(_p(xy), len(xy), int(c), _p(v)))
 
 
+def x_sweep_index(xy):
+    """(xorder, xpos): the cities by ascending x and each city's place in that order,
+    for the sweep form of the nearest-unvisited search used when checking long tours."""
+    xy = _xy(xy)
+    order = np.argsort(xy[:, 0], kind="stable").astype(np.int32)
+    pos = np.empty(len(xy), np.int32)
+    pos[order] = np.arange(len(xy), dtype=np.int32)
+    return order, pos
+
+
+def nearest_unvisited_sweep(xy, c: int, visited, index=None) -> int:
+    """The nearest unvisited city by a sweep along x (same result as the brute force)."""
+    xy = _xy(xy)
+    order, pos = x_sweep_index(xy) if index is None else index
+    v = np.ascontiguousarray(visited, np.uint8)
+    return int(lib().oracle_nearest_unvisited_sweep(_p(xy), len(xy), int(c), _p(v), _p(order),
+                                                     _p(pos)))
+
+
 def nn_tour(xy, nn, nnd):
     xy = _xy(xy)
     nn = np.ascontiguousarray(nn, np.int32)
@@ -241,8 +263,10 @@ REPLAY_FIELDS = ("steps", "fallbacks", "near_boundary_mismatch", "hard_mismatch"
 
 
 def replay(xy, nn, nnd, tau, alpha, beta, seed, iteration, ant, tour, eta=None,
-           boundary_eps=1e-6):
-    """Teacher-forced replay of one tour.  Returns (counts dict, prob float64 [n])."""
+           boundary_eps=1e-6, sweep=None):
+    """Teacher-forced replay of one tour.  Returns (counts dict, prob float64 [n]).
+    sweep: None (fallback moves checked by the O(n) brute force) or the
+    x_sweep_index of xy (checked by the sweep along x, which gives the same city)."""
     xy = _xy(xy)
     n = len(xy)
     nn = np.ascontiguousarray(nn, np.int32)
@@ -252,9 +276,10 @@ def replay(xy, nn, nnd, tau, alpha, beta, seed, iteration, ant, tour, eta=None,
     tour = np.ascontiguousarray(tour, np.int32)
     prob = np.zeros(n, np.float64)
     out = np.zeros(8, np.int64)
+    order, pos = (None, None) if sweep is None else sweep
     lib().oracle_replay(n, nn.shape[1], _p(xy), _p(nn), _p(nnd), _p(tau), _p(eta), float(alpha),
                         float(beta), int(seed), int(iteration), int(ant), _p(tour),
-                        float(boundary_eps), _p(prob), _p(out))
+                        float(boundary_eps), _p(order), _p(pos), _p(prob), _p(out))
     return {f: int(out[i]) for i, f in enumerate(REPLAY_FIELDS)}, prob
 
 
@@ -382,17 +407,25 @@ def update_local_best(lbest, lbest_len, tours, lengths):
 
 
 # ---------------------------------------------------------------- update
-def deposit(nn, tours, lengths, shift=32) -> np.ndarray:
+def deposit(nn, tours, lengths, shift=32, threads=None) -> np.ndarray:
     nn = np.ascontiguousarray(nn, np.int32)
     tours = np.ascontiguousarray(tours, np.int32)
     lengths = np.ascontiguousarray(lengths, np.int64)
     n, k = nn.shape
     acc = np.empty((n, k), np.int64)
-    lib().oracle_deposit(n, k, _p(nn), tours.shape[0], _p(tours), _p(lengths), int(shift), _p(acc))
+    lib().oracle_deposit(n, k, _p(nn), tours.shape[0], _p(tours), _p(lengths), int(shift), _p(acc),
+                         _update_threads(threads, tours.shape[0]))
     return acc
 
 
-def update(nn, tau, tours, lengths, rho, shift=32) -> np.ndarray:
+def _update_threads(threads, m) -> int:
+    """Threads for the deposit: one for small colonies, else up to 16."""
+    if threads:
+        return int(threads)
+    return 1 if m < 64 else min(16, os.cpu_count() or 1)
+
+
+def update(nn, tau, tours, lengths, rho, shift=32, threads=None) -> np.ndarray:
     """Return the pheromone after evaporation and deposit (input left untouched)."""
     nn = np.ascontiguousarray(nn, np.int32)
     t = np.array(tau, dtype=np.float32, copy=True, order="C")
@@ -400,7 +433,7 @@ def update(nn, tau, tours, lengths, rho, shift=32) -> np.ndarray:
     lengths = np.ascontiguousarray(lengths, np.int64)
     n, k = nn.shape
     lib().oracle_update(n, k, _p(nn), _p(t), tours.shape[0], _p(tours), _p(lengths), float(rho),
-                        int(shift))
+                        int(shift), _update_threads(threads, tours.shape[0]))
     return t
 
 

@@ -225,6 +225,44 @@ int64_t oracle_nearest_unvisited(const int32_t *xy, int64_t n, int64_t c, const 
     return nearest_unvisited(xy, n, c, vis, &d);
 }
 
+/* The same minimum key, found by a sweep outward from c along the cities in
+ * order of x: a shortcut for checking long tours, pinned against the brute
+ * force above.  xorder lists every city by ascending x (any order among
+ * equal x) and xpos[c] is c's place in that list.  A city with
+ * |x_j - x_c| > D (integers) has sqrt(s) >= D + 1 and so d_cj > D: once the
+ * nearer of the two next cities is further than the best distance found in
+ * x alone, no remaining city can have a smaller or equal distance. */
+static int64_t nearest_unvisited_sweep(const int32_t *xy, int64_t n, int64_t c,
+                                       const uint8_t *vis, const int32_t *xorder,
+                                       const int32_t *xpos, int64_t *d_out)
+{
+    int64_t best = -1, bd = 0;
+    int64_t lo = (int64_t)xpos[c] - 1, hi = (int64_t)xpos[c] + 1;
+    int64_t xc = xy[2 * c];
+    for (;;) {
+        int64_t dl = lo >= 0 ? xc - xy[2 * (int64_t)xorder[lo]] : -1;   /* >= 0 when present */
+        int64_t dh = hi < n ? xy[2 * (int64_t)xorder[hi]] - xc : -1;
+        if (dl < 0 && dh < 0) break;
+        int use_lo = dh < 0 || (dl >= 0 && dl <= dh);
+        int64_t dx = use_lo ? dl : dh;
+        if (best >= 0 && dx > bd) break;
+        int64_t j = xorder[use_lo ? lo-- : hi++];
+        if (vis[j]) continue;
+        int64_t d = oracle_dist(xy, c, j);
+        if (best < 0 || d < bd || (d == bd && j < best)) { best = j; bd = d; }
+    }
+    *d_out = bd;
+    return best;
+}
+
+int64_t oracle_nearest_unvisited_sweep(const int32_t *xy, int64_t n, int64_t c,
+                                       const uint8_t *vis, const int32_t *xorder,
+                                       const int32_t *xpos)
+{
+    int64_t d;
+    return nearest_unvisited_sweep(xy, n, c, vis, xorder, xpos, &d);
+}
+
 /* ------------------------------------------------------------------ */
 /* Nearest-neighbour tour from city 0 (pheromone initialisation).       */
 /* Each step takes the unvisited city with the smallest (d, j).  Every  */
@@ -293,6 +331,8 @@ typedef struct {
     uint64_t seed;
     int64_t iteration;
     int sampler;             /* 0: roulette of Eq. 1; 1: Independent Roulette (Section 3) */
+    const int32_t *xorder;   /* replay only: cities by x for the sweep check, or NULL */
+    const int32_t *xpos;
 } colony_t;
 
 /* Heuristic eta_ir = 1/d_ir (Section 2); d = 0 (coincident cities) is read as 1. */
@@ -491,10 +531,14 @@ static void replay_from(const colony_t *C, int64_t ant, const int32_t *tour, int
                 else out[3]++;
             }
         } else {
-            int64_t d;
+            int64_t d, want;
             out[1]++;
             prob[t] = -1.0;
-            if (nearest_unvisited(C->xy, n, c, vis, &d) != j) out[4]++;
+            if (C->xorder)
+                want = nearest_unvisited_sweep(C->xy, n, c, vis, C->xorder, C->xpos, &d);
+            else
+                want = nearest_unvisited(C->xy, n, c, vis, &d);
+            if (want != j) out[4]++;
         }
         vis[j] = 1;
         c = j;
@@ -636,6 +680,8 @@ void oracle_construct_partial(int64_t n, int k, const int32_t *xy, const int32_t
     C.n = n; C.k = k; C.xy = xy; C.nn = nn; C.nnd = nnd; C.tau = tau; C.eta = eta;
     C.alpha = alpha; C.beta = beta; C.seed = seed; C.iteration = iteration;
     C.sampler = sampler;
+    C.xorder = NULL;
+    C.xpos = NULL;
     for (int64_t q = 0; q < count; q++) {
         ant_result_t r = construct_partial_ant(&C, ants[q], lbest + q * n, p_threshold,
                                                max_modify, tours + q * n,
@@ -661,6 +707,8 @@ void oracle_replay_partial(int64_t n, int k, const int32_t *xy, const int32_t *n
     C.n = n; C.k = k; C.xy = xy; C.nn = nn; C.nnd = nnd; C.tau = tau; C.eta = eta;
     C.alpha = alpha; C.beta = beta; C.seed = seed; C.iteration = iteration;
     C.sampler = sampler;
+    C.xorder = NULL;
+    C.xpos = NULL;
     int64_t s, r;
     int partial;
     oracle_partial_plan(seed, iteration, ant, n, p_threshold, max_modify, &s, &partial, &r);
@@ -830,11 +878,12 @@ static void deposit_quanta(int64_t n, int k, const int32_t *nn, int64_t m, const
     }
 }
 
-void oracle_deposit(int64_t n, int k, const int32_t *nn, int64_t m, const int32_t *tours,
-                    const int64_t *lengths, int shift, int64_t *acc)
+/* The deposit of ants a0..a1-1 into acc (zeroed first). */
+static void deposit_ants(int64_t n, int k, const int32_t *nn, int64_t a0, int64_t a1,
+                         const int32_t *tours, const int64_t *lengths, int shift, int64_t *acc)
 {
     memset(acc, 0, (size_t)(n * k) * sizeof(int64_t));
-    for (int64_t a = 0; a < m; a++) {
+    for (int64_t a = a0; a < a1; a++) {
         int64_t q = ((int64_t)1 << shift) / lengths[a];
         const int32_t *T = tours + a * n;
         for (int64_t t = 0; t < n; t++) {
@@ -847,11 +896,48 @@ void oracle_deposit(int64_t n, int k, const int32_t *nn, int64_t m, const int32_
     }
 }
 
+typedef struct {
+    int64_t n; int k; const int32_t *nn; int64_t a0, a1;
+    const int32_t *tours; const int64_t *lengths; int shift; int64_t *acc;
+} deposit_job_t;
+
+static void *deposit_worker(void *arg)
+{
+    deposit_job_t *J = (deposit_job_t *)arg;
+    deposit_ants(J->n, J->k, J->nn, J->a0, J->a1, J->tours, J->lengths, J->shift, J->acc);
+    return NULL;
+}
+
+/* Threads take contiguous groups of ants into private sums, added at the end:
+ * integer addition, so the result does not depend on the split. */
+void oracle_deposit(int64_t n, int k, const int32_t *nn, int64_t m, const int32_t *tours,
+                    const int64_t *lengths, int shift, int64_t *acc, int threads)
+{
+    if (threads > m) threads = (int)m;
+    if (threads > 64) threads = 64;
+    if (threads <= 1) {
+        deposit_ants(n, k, nn, 0, m, tours, lengths, shift, acc);
+        return;
+    }
+    deposit_job_t job[64];
+    pthread_t th[64];
+    for (int t = 0; t < threads; t++) {
+        job[t] = (deposit_job_t){n, k, nn, m * t / threads, m * (t + 1) / threads, tours, lengths,
+                                 shift, t == 0 ? acc : (int64_t *)malloc((size_t)(n * k) * 8)};
+        pthread_create(&th[t], NULL, deposit_worker, &job[t]);
+    }
+    for (int t = 0; t < threads; t++) pthread_join(th[t], NULL);
+    for (int t = 1; t < threads; t++) {
+        for (int64_t e = 0; e < n * k; e++) acc[e] += job[t].acc[e];
+        free(job[t].acc);
+    }
+}
+
 void oracle_update(int64_t n, int k, const int32_t *nn, float *tau, int64_t m, const int32_t *tours,
-                   const int64_t *lengths, double rho, int shift)
+                   const int64_t *lengths, double rho, int shift, int threads)
 {
     int64_t *acc = (int64_t *)malloc((size_t)(n * k) * sizeof(int64_t));
-    oracle_deposit(n, k, nn, m, tours, lengths, shift, acc);
+    oracle_deposit(n, k, nn, m, tours, lengths, shift, acc, threads);
     float f = (float)(1.0 - rho);
     float scale = ldexpf(1.0f, -shift);
     for (int64_t e = 0; e < n * k; e++) {
@@ -904,6 +990,8 @@ static void colony_init(colony_t *C, int64_t n, int k, const int32_t *xy, const 
     C->n = n; C->k = k; C->xy = xy; C->nn = nn; C->nnd = nnd; C->tau = tau; C->eta = eta;
     C->alpha = alpha; C->beta = beta; C->seed = seed; C->iteration = iteration;
     C->sampler = 0;
+    C->xorder = NULL;
+    C->xpos = NULL;
 }
 
 /* Construct the ants listed in `ants` (count of them); outputs are [count][n]. */
@@ -927,10 +1015,12 @@ void oracle_construct(int64_t n, int k, const int32_t *xy, const int32_t *nn, co
 void oracle_replay(int64_t n, int k, const int32_t *xy, const int32_t *nn, const int32_t *nnd,
                    const float *tau, const double *eta, double alpha, double beta, uint64_t seed,
                    int64_t iteration, int64_t ant, const int32_t *tour, double boundary_eps,
-                   double *prob, int64_t *out)
+                   const int32_t *xorder, const int32_t *xpos, double *prob, int64_t *out)
 {
     colony_t C;
     colony_init(&C, n, k, xy, nn, nnd, tau, eta, alpha, beta, seed, iteration);
+    C.xorder = xorder;
+    C.xpos = xpos;
     oracle_replay_ant(&C, ant, tour, boundary_eps, prob, out);
 }
 
@@ -974,7 +1064,7 @@ int oracle_run(int64_t n, int k, const int32_t *xy, int64_t m, double alpha, dou
             *best_len = lengths[ib];
             memcpy(best_tour, tours + ib * n, (size_t)n * 4);
         }
-        oracle_update(n, k, nn, tau, m, tours, lengths, rho, shift);
+        oracle_update(n, k, nn, tau, m, tours, lengths, rho, shift, threads);
     }
     if (tau_out) memcpy(tau_out, tau, (size_t)(n * k) * 4);
     free(nn); free(nnd); free(rows); free(tau); free(tours); free(lengths); free(ants);

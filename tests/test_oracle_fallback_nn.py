@@ -50,3 +50,84 @@ def test_nn_tour_shortcut_equals_plain(orc, n, k, span):
 
 def test_tau0(orc):
     assert orc.tau0(1000, 123456) == np.float32(1.0 / (1000.0 * 123456.0))
+
+
+def _sweep_cases():
+    line = np.stack([np.arange(300) * 7 % 1000, np.zeros(300)], 1).astype(np.int32)
+    column = np.stack([np.zeros(300), np.arange(300) * 11 % 1000], 1).astype(np.int32)
+    return {
+        "uniform": instances.uniform_coords(400, 31),
+        "ties": instances.uniform_coords(500, 17, hi=30),        # duplicates, equal distances
+        "tiny_span": instances.uniform_coords(300, 5, hi=3),
+        "line": line,
+        "column": column,                                        # every x equal
+        "negative": instances.uniform_coords(400, 4, hi=2 * 10**8) - 10**8,
+        "clustered": instances.clustered_coords(2000, 9, clusters=7, sigma=2e3),
+    }
+
+
+@pytest.mark.parametrize("name", list(_sweep_cases()))
+def test_fallback_sweep_equals_brute_force(orc, name):
+    """The sweep along x (used to check fallback moves of long tours) finds the
+    same city as the brute-force argmin of (d, j), on random visited sets from
+    nearly empty to nearly full."""
+    xy = _sweep_cases()[name]
+    n = len(xy)
+    idx = orc.x_sweep_index(xy)
+    rng = np.random.default_rng(len(name))
+    D = nint_matrix(xy)
+    for trial in range(300):
+        frac = [0.0, 0.5, 0.9, 0.99, 0.999][trial % 5]
+        vis = (rng.random(n) < frac).astype(np.uint8)
+        c = int(rng.integers(n))
+        vis[c] = 1
+        if vis.all():
+            continue
+        a = orc.nearest_unvisited_sweep(xy, c, vis, idx)
+        un = np.nonzero(vis == 0)[0]
+        ref = un[np.lexsort((un, D[c][un]))[0]]
+        assert a == ref == orc.nearest_unvisited(xy, c, vis), (name, trial)
+
+
+def test_fallback_sweep_equals_brute_force_clustered_200k(orc):
+    """The same on the clustered 200K instance, along a tour-like visiting order
+    (the sets a long tour's fallbacks meet)."""
+    xy = instances.make_coords("c3")
+    n = len(xy)
+    idx = orc.x_sweep_index(xy)
+    rng = np.random.default_rng(3)
+    order = rng.permutation(n)
+    for frac in (0.01, 0.3, 0.7, 0.95, 0.9999):
+        vis = np.zeros(n, np.uint8)
+        vis[order[:int(frac * n)]] = 1
+        for c in rng.choice(order[:max(1, int(frac * n))], 4, replace=False):
+            a = orc.nearest_unvisited_sweep(xy, int(c), vis, idx)
+            b = orc.nearest_unvisited(xy, int(c), vis, plain=True)
+            assert a == b, (frac, c)
+
+
+def test_replay_with_sweep_matches_brute_force_replay(orc):
+    """Replaying a constructed tour gives the same counts and probabilities with
+    either form of the fallback check, and a wrong fallback move is caught by both."""
+    xy = instances.clustered_coords(3000, 8, clusters=5, sigma=3e3)
+    n, k = len(xy), 8
+    nn, nnd = orc.knn_rows(xy, k)
+    L = orc.nn_tour(xy, nn, nnd)[1]
+    tau = np.full((n, k), orc.tau0(n, L), np.float32)
+    r = orc.construct(xy, nn, nnd, tau, 1.0, 2.0, 5, 0, [3], want_slots=True)
+    tour = r["tours"][0]
+    assert r["fallbacks"][0] > 10
+    idx = orc.x_sweep_index(xy)
+    c1, p1 = orc.replay(xy, nn, nnd, tau, 1.0, 2.0, 5, 0, 3, tour)
+    c2, p2 = orc.replay(xy, nn, nnd, tau, 1.0, 2.0, 5, 0, 3, tour, sweep=idx)
+    assert c1 == c2 and c1["fallback_mismatch"] == 0 and c1["fallbacks"] == r["fallbacks"][0]
+    np.testing.assert_array_equal(p1, p2)
+    # swap the city of a late fallback step with the next one: a wrong nearest city
+    fb = np.nonzero(r["slots"][0] < 0)[0]
+    t = int(fb[fb < n - 2][-1])
+    bad = tour.copy()
+    bad[t], bad[t + 1] = bad[t + 1], bad[t]
+    d1, _ = orc.replay(xy, nn, nnd, tau, 1.0, 2.0, 5, 0, 3, bad)
+    d2, _ = orc.replay(xy, nn, nnd, tau, 1.0, 2.0, 5, 0, 3, bad, sweep=idx)
+    assert d1 == d2
+    assert d1["fallback_mismatch"] + d1["hard_mismatch"] >= 1

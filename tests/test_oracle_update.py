@@ -118,3 +118,19 @@ def test_run_best_tracking_and_determinism(orc):
     L_nn = orc.nn_tour(xy, nn, nnd)[1]
     assert r1["best_len"] == min(L_nn, int(r1["iter_best"].min()))
     assert np.array_equal(np.sort(r1["best_tour"]), np.arange(300))
+
+
+def test_deposit_threads_do_not_change_the_sums(orc):
+    """Threads over groups of ants give the same exact int64 sums as one thread."""
+    xy = instances.uniform_coords(600, 77)
+    nn, _ = orc.knn_rows(xy, 9)
+    rng = np.random.default_rng(5)
+    tours = np.stack([rng.permutation(600) for _ in range(70)]).astype(np.int32)
+    tours[:10] = tours[0]                       # shared edges across thread groups
+    lengths = rng.integers(10**5, 10**7, 70)
+    one = orc.deposit(nn, tours, lengths, 32, threads=1)
+    for t in (2, 3, 16, 70):
+        np.testing.assert_array_equal(orc.deposit(nn, tours, lengths, 32, threads=t), one)
+    tau = np.full((600, 9), np.float32(1e-9))
+    np.testing.assert_array_equal(orc.update(nn, tau, tours, lengths, 0.1, 32, threads=1),
+                                  orc.update(nn, tau, tours, lengths, 0.1, 32, threads=7))
