@@ -18,3 +18,13 @@ def orc():
     import oracle
     oracle.lib()
     return oracle
+
+
+@pytest.fixture
+def report(capsys):
+    """Print a line to the terminal even while pytest captures output (the
+    replay counts of the full-size parity tests belong in the run's log)."""
+    def emit(msg):
+        with capsys.disabled():
+            print(msg, flush=True)
+    return emit

@@ -40,22 +40,26 @@ def to_np(t):
     return t.detach().cpu().numpy()
 
 
-def replay_ants(xy, nn, nnd, tau, alpha, beta, seed, iteration, tours, ants, eta=None):
+def replay_ants(xy, nn, nnd, tau, alpha, beta, seed, iteration, tours, ants, eta=None,
+                sweep=None):
     """Replay every given GPU tour with the oracle; returns (per-ant counts, probs)."""
     def one(q):
         return orc.replay(xy, nn, nnd, tau, alpha, beta, seed, iteration, int(ants[q]), tours[q],
-                          eta=eta, boundary_eps=BOUNDARY_EPS)
+                          eta=eta, boundary_eps=BOUNDARY_EPS, sweep=sweep)
     with ThreadPoolExecutor(max_workers=threads()) as ex:
         res = list(ex.map(one, range(len(ants))))
     return [r[0] for r in res], np.stack([r[1] for r in res])
 
 
 def check_tours(xy, nn, nnd, tau, alpha, beta, seed, iteration, tours, lengths, slots, probs,
-                ants, eta=None, label=""):
-    """Full parity check of GPU tours for one iteration.  Returns the summed counts."""
+                ants, eta=None, label="", sweep=None):
+    """Full parity check of GPU tours for one iteration.  Returns the summed counts.
+    sweep: the oracle's x_sweep_index, to check fallback moves by its sweep along x
+    (same city as its brute force) instead of the O(n) scan."""
     n = len(xy)
     k = nn.shape[1]
-    counts, oprob = replay_ants(xy, nn, nnd, tau, alpha, beta, seed, iteration, tours, ants, eta)
+    counts, oprob = replay_ants(xy, nn, nnd, tau, alpha, beta, seed, iteration, tours, ants, eta,
+                                sweep)
     tot = {f: sum(c[f] for c in counts) for f in counts[0]}
     assert tot["invalid"] == 0, (label, tot)
     assert tot["hard_mismatch"] == 0, (label, tot)

@@ -70,7 +70,7 @@ def test_candidates_c2():
 
 
 def run_and_check(xy, k, m, alpha, beta, rho, iterations, seed, shift=32, tau_noise=False,
-                  label=""):
+                  label="", report=None):
     """Iterate on the GPU; every iteration replay all ants with the oracle and
     check the pheromone bit-exactly against the oracle's update."""
     import torch
@@ -103,6 +103,9 @@ def run_and_check(xy, k, m, alpha, beta, rho, iterations, seed, shift=32, tau_no
         torch.cuda.synchronize()
         tau = orc.update(nn, tau, tours, [orc.tour_length(xy, t) for t in tours], rho, shift)
         np.testing.assert_array_equal(to_np(col.tau), tau, err_msg=f"{label} it {it} tau")
+        if report:
+            report(f"\n[{label}] iteration {it}: oracle replayed all {m} ants, {tot}; "
+                   f"pheromone bit-exact")
     say(f"[run] {label} totals {totals}")
     return totals
 
@@ -129,11 +132,11 @@ def test_edge_cases_run(name):
     run_and_check(xy, k, 8, 1.0, 2.0, 0.1, 2, 5, tau_noise=True, label=name)
 
 
-def test_c2_iterations():
+def test_c2_iterations(report):
     cfg = instances.CONFIGS["c2"]
     xy = instances.make_coords("c2")
-    tot = run_and_check(xy, cfg["k"], cfg["m"], cfg["alpha"], cfg["beta"], cfg["rho"], 2,
-                        cfg["seed"], label="c2")
+    tot = run_and_check(xy, cfg["k"], cfg["m"], cfg["alpha"], cfg["beta"], cfg["rho"], 5,
+                        cfg["seed"], label="c2", report=report)
     assert tot["near_boundary_mismatch"] <= 1e-4 * tot["steps"]
 
 
