@@ -10,6 +10,9 @@ Prints one JSON line.  `value` = ant-steps per second over whole iterations,
 m * (n - 1) ant-steps per iteration.  `roofline` prices the construction
 kernel by its algorithmic bytes per ant-step.  `cpu_baseline` times the CPU
 oracle (threads over ants) on a fixed sample of ants of the same workload.
+`equal_time_c1` and `equal_time_c2` run the GPU and the oracle to
+completion on n = 1,000 and n = 20,000 and compare their bests at the GPU's
+wall time and at equal iterations.
 Further objects report the batched colonies (4,096 instances, one
 persistent launch, autotuned), the learned heuristic (training on the GPU,
 kernel rates, and the equal-wall-clock comparison with plain eta) and
@@ -57,23 +60,52 @@ TRAFFIC_SOURCES = ["paper_1709_03187_amd/csrc/construct.hip",
                    "paper_1709_03187_amd/csrc/colony.hpp",
                    "paper_1709_03187_amd/csrc/device.hpp",
                    "paper_1709_03187_amd/csrc/common.hpp"]
+BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_batched_c4_4096inst_m64_k12.md")
+BATCH_TRAFFIC_SOURCES = ["paper_1709_03187_amd/csrc/batch.hip",
+                         "paper_1709_03187_amd/csrc/colony.hpp",
+                         "paper_1709_03187_amd/csrc/colony_x4.hpp",
+                         "paper_1709_03187_amd/csrc/device.hpp",
+                         "paper_1709_03187_amd/csrc/common.hpp"]
+# Random 64-bit atomic adds per second on one MI355X (a probe of 2^27 hashed
+# adds from 8,192 workgroups; the same from 1 MiB to 256 MiB buffers).
+ATOMIC_RATE_PROBE = 23.7e9
+
+
+def counter_summary(path, sources):
+    """Fields of a committed counter summary, or None when the sources it was
+    taken from changed since (hash mismatch) or it is missing."""
+    import hashlib
+    try:
+        fields = dict(line.split(": ", 1) for line in open(path).read().splitlines()
+                      if ": " in line and not line.startswith(("|", "#", " ")))
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for s in sources:
+        h.update(open(os.path.join(ROOT, s), "rb").read())
+    if fields.get("source_sha256") != h.hexdigest():
+        return None
+    return fields
 
 
 def measured_traffic_bytes():
     """HBM bytes per construction launch from the committed counter summary,
     or None when the construction sources changed since it was taken."""
-    import hashlib
-    try:
-        fields = dict(line.split(": ", 1) for line in open(TRAFFIC_FILE).read().splitlines()
-                      if ": " in line and not line.startswith(("|", "#", " ")))
-    except OSError:
-        return None
-    h = hashlib.sha256()
-    for s in TRAFFIC_SOURCES:
-        h.update(open(os.path.join(ROOT, s), "rb").read())
-    if fields.get("source_sha256") != h.hexdigest():
-        return None
-    return float(fields["stage_traffic_bytes_per_launch"])
+    f = counter_summary(TRAFFIC_FILE, TRAFFIC_SOURCES)
+    return None if f is None else float(f["stage_traffic_bytes_per_launch"])
+
+
+def batched_bytes_per_iteration(sizes, m: int, k: int) -> int:
+    """Algorithmic bytes of one iteration of the batched colonies: per ant-step
+    the row (8k), tour entry, slot and the edge's distance (9 B, as the single
+    instance); per tour edge the deposit (tour entry, slot, reverse slot and
+    one int64 atomic on the canonical slot, written back: 22 B); per candidate
+    slot the merge, the cleared sum and the next choice weights (32 B)."""
+    sizes = np.asarray(sizes, np.int64)
+    steps = int((m * (sizes - 1)).sum())
+    edges = int((m * sizes).sum())
+    slots = int(sizes.sum()) * k
+    return steps * (8 * k + 9) + edges * 22 + slots * 32
 
 
 def log(msg):
@@ -119,6 +151,100 @@ def cpu_baseline(xy, cfg, tau0_gpu, threads, ants_per_thread=4):
                 fallback_share=float(res["fallbacks"].sum() / (count * (n - 1))))
 
 
+def deposit_atomics(col) -> int:
+    """Atomics one pheromone update issues for the colony's current tours: one
+    per tour edge {i, j} with j in nn[i] or i in nn[j] (its canonical slot)."""
+    import torch
+    tours = col.tours.long()
+    nxt = torch.roll(tours, -1, dims=1)
+    fwd = torch.zeros_like(tours, dtype=torch.bool)
+    fwd[:, :-1] = col.slots[:, 1:] != 255            # recorded candidate moves
+    i, j = tours[~fwd], nxt[~fwd]                     # fallback moves and closing edges
+    nn = col.nn.long()
+    hit = torch.zeros(i.numel(), dtype=torch.bool, device=i.device)
+    for c0 in range(0, i.numel(), 1 << 22):
+        a, b = i[c0:c0 + (1 << 22)], j[c0:c0 + (1 << 22)]
+        hit[c0:c0 + a.numel()] = ((nn[a] == b[:, None]).any(1) | (nn[b] == a[:, None]).any(1))
+    return int(fwd.sum().item() + hit.sum().item())
+
+
+def equal_time_block(name, threads):
+    """Equal-time and equal-iteration comparison on a workload the oracle runs
+    to completion (n = 1,000 and n = 20,000 uniform).
+
+    Both sides run the same loop with the same Philox keys: NN-tour
+    initialisation, then every iteration (construction, best tracking,
+    update).  Candidate lists are built first on both sides and not counted
+    (the oracle's are an O(n^2) brute force).  The best so far is stamped
+    after each iteration on each side's own clock.  T is the GPU's time for
+    the whole loop; the oracle's best at T is the best it had reached by
+    then (its NN tour once built).  The equal-iteration figures compare the
+    final bests, and the oracle's time to finish against the GPU's."""
+    import torch
+
+    import oracle as orc
+    import paper_1709_03187_amd as aco
+    from paper_1709_03187_amd import instances
+
+    cfg = instances.CONFIGS[name]
+    xy = instances.make_coords(name)
+    n, m, k, iters = cfg["n"], cfg["m"], cfg["k"], cfg["iterations"]
+    # GPU
+    col = aco.Colony(xy=xy, k=k, m=m, alpha=cfg["alpha"], beta=cfg["beta"], rho=cfg["rho"],
+                     seed=cfg["seed"])
+    col.build_candidates()
+    torch.cuda.synchronize()
+    t0 = time.time()
+    col.init_pheromone()
+    torch.cuda.synchronize()
+    gpu_marks = [(time.time() - t0, col.L_nn)]
+    for it in range(iters):
+        col.iterate(it)
+        torch.cuda.synchronize()
+        gpu_marks.append((time.time() - t0, int(col.best_len.item())))
+    T = gpu_marks[-1][0]
+    gpu_best = gpu_marks[-1][1]
+    del col
+    torch.cuda.empty_cache()
+    # oracle
+    t0 = time.time()
+    nn, nnd = orc.knn_rows(xy, k, threads=threads)
+    knn_s = time.time() - t0
+    t0 = time.time()
+    L_nn = orc.nn_tour(xy, nn, nnd)[1]
+    tau = np.full((n, k), orc.tau0(n, L_nn), np.float32)
+    best = L_nn
+    or_marks = [(time.time() - t0, best)]
+    for it in range(iters):
+        r = orc.construct(xy, nn, nnd, tau, cfg["alpha"], cfg["beta"], cfg["seed"], it,
+                          np.arange(m), threads=threads)
+        tau = orc.update(nn, tau, r["tours"], r["lengths"], cfg["rho"], 32, threads=threads)
+        best = min(best, int(r["lengths"].min()))
+        or_marks.append((time.time() - t0, best))
+        log(f"[bench] {name} oracle iteration {it} done ({or_marks[-1][0]:.1f} s)")
+    at_T = [mk for mk in or_marks if mk[0] <= T]
+    or_best_T = at_T[-1][1] if at_T else None
+    or_best = or_marks[-1][1]
+    return {
+        "workload": f"n={n:,} uniform integer cities in [0,1e6]^2, m={m}, k={k}, alpha=1, "
+                    f"beta=2, rho=0.1, {iters} iterations, Philox seed {cfg['seed']}",
+        "equal_time": {
+            "seconds": T, "gpu_best": gpu_best,
+            "oracle_best": or_best_T,
+            "oracle_iterations_done": max(0, len(at_T) - 1),
+            "gap": None if or_best_T is None else (gpu_best - or_best_T) / or_best_T},
+        "equal_iterations": {
+            "iterations": iters, "gpu_best": gpu_best, "oracle_best": or_best,
+            "gap": (gpu_best - or_best) / or_best,
+            "gpu_seconds": T, "oracle_seconds": or_marks[-1][0],
+            "oracle_over_gpu_time": or_marks[-1][0] / T},
+        "gpu_best_by_iteration": [v for _, v in gpu_marks],
+        "oracle_best_by_iteration": [v for _, v in or_marks],
+        "candidate_lists_not_counted_s": {"oracle": knn_s},
+        "oracle_threads": threads,
+    }
+
+
 def batched_block():
     """The batched workload: 4,096 instances, n log-uniform in [100, 5,000],
     m = 64, k = 12, 30 iterations, one persistent launch per run.  The first
@@ -152,9 +278,20 @@ def batched_block():
     ms = e0.elapsed_time(e1)
     steps = int(cfg["m"] * (sizes - 1).sum()) * iters
     L0 = bt.best_lens.cpu().numpy()
+    alg = batched_bytes_per_iteration(sizes, cfg["m"], cfg["k"]) * iters
+    achieved = alg / (ms * 1e-3) / 1e9
+    cs = counter_summary(BATCH_TRAFFIC_FILE, BATCH_TRAFFIC_SOURCES)
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None if cs is None else float(cs["launch_traffic_bytes"]) / (ms * 1e-3) / 1e9,
+            "l2_hit_rate": None if cs is None else float(cs["l2_hit_rate"]),
+            "kernel": "k_b_colony (all 30 iterations: construction, lengths, deposit, merge, "
+                      "choice weights)",
+            "algorithmic_bytes_per_launch": alg,
+            "traffic_bytes_per_launch": None if cs is None else float(cs["launch_traffic_bytes"])}
     return {"workload": f"{bt.B} instances, n log-uniform in [100, 5000] (sum {bt.N}), m=64, "
                         f"k=12, 30 iterations, one persistent launch",
-            "ant_steps_per_s": steps / (ms * 1e-3), "launch_ms": ms,
+            "ant_steps_per_s": steps / (ms * 1e-3), "launch_ms": ms, "roofline": roof,
             "ms_per_iteration": ms / iters, "setup_ms": t_setup * 1e3,
             "first_run_with_tuning_s": t_tuned_run,
             "tuned": {"waves_per_instance": tuned[0],
@@ -212,14 +349,21 @@ def _colony_until(xy, cfg, beta, budget_s, iterations, theta=None):
     return res
 
 
+LEARNED_BETAS = (2.0, 4.0, 8.0, 12.0)
+
+
 def learned_block(xy_eval, cfg):
     """Learned heuristic: 64 uniform n=20,000 instances (seeds 1000..1063) are
-    solved by the batched colonies (m=64, k=16, 30 iterations, beta=2); the
-    candidate edges of their best tours are the positive labels.  3,000 Adam
-    steps of 65,536 edges train the network.  Then the evaluation workload
-    runs with plain eta (beta=2, its 20 iterations: wall clock T) and with the
-    learned score (beta=8, chosen on held-out uniform instances) for the same
-    T, set-up included; plain eta at beta=8 is reported beside it."""
+    solved by the batched colonies (m=64, k=16, 30 iterations, beta=2) and
+    each best tour is made 2-optimal within a window of 1,000 positions; its
+    candidate edges are the positive labels.  3,000 Adam steps of 65,536
+    edges train the network.  Each heuristic (plain eta = 1/d, learned score)
+    then gets its own best beta from {2, 4, 8, 12}, chosen on two held-out
+    uniform n=20,000 instances (m=256, 30 iterations); on the evaluation
+    workload plain eta at its beta runs its 20 iterations (wall clock T, set-up
+    included) and the learned score at its beta runs for the same T.  Plain
+    eta at the learned score's beta, and both at beta=2, run for T beside
+    them."""
     import torch
 
     import paper_1709_03187_amd as aco
@@ -227,7 +371,7 @@ def learned_block(xy_eval, cfg):
 
     k = cfg["k"]
     xys = [instances.uniform_coords(20000, 1000 + b) for b in range(64)]
-    data = learned.training_set(xys, k=k, m=64, iterations=30, seed=1)
+    data = learned.training_set(xys, k=k, m=64, iterations=30, seed=1, two_opt_window=1000)
     E = int(data.feat.shape[0])
     set_s = data.seconds
     tr = learned.train(data, instances.mlp_parameters(0), steps=3000, batch=65536, lr=2e-3,
@@ -251,19 +395,34 @@ def learned_block(xy_eval, cfg):
                                                    feat, fws), 20)
     del col, feat
     torch.cuda.empty_cache()
+    # beta chosen per heuristic on held-out instances
+    held = [instances.uniform_coords(20000, 5000 + b) for b in range(2)]
+    hcfg = dict(cfg, m=256)
+    sel = {"plain": {}, "learned": {}}
+    for beta in LEARNED_BETAS:
+        for name, th in (("plain", None), ("learned", theta)):
+            sel[name][beta] = float(np.mean([_colony_until(x, hcfg, beta, None, 30, theta=th)
+                                             ["best_len"] for x in held]))
+    b_plain = min(LEARNED_BETAS, key=lambda b: sel["plain"][b])
+    b_lrn = min(LEARNED_BETAS, key=lambda b: sel["learned"][b])
     its = cfg["iterations"]
-    plain = _colony_until(xy_eval, cfg, cfg["beta"], None, its)
+    plain = _colony_until(xy_eval, cfg, b_plain, None, its)
     T = plain["seconds"]
-    lrn = _colony_until(xy_eval, cfg, 8.0, T, 100 * its, theta=theta)
-    plain8 = _colony_until(xy_eval, cfg, 8.0, T, 100 * its)
+    lrn = _colony_until(xy_eval, cfg, b_lrn, T, 100 * its, theta=theta)
+    plain_same = _colony_until(xy_eval, cfg, b_lrn, T, 100 * its)
+    plain2 = _colony_until(xy_eval, cfg, 2.0, T, 100 * its)
+    lrn2 = _colony_until(xy_eval, cfg, 2.0, T, 100 * its, theta=theta)
     fwd_tflops = MLP_FLOP_FORWARD * Ev / (fwd_ms * 1e-3) / 1e12
     bwd_tflops = MLP_FLOP_BACKWARD * B / (bwd_ms * 1e-3) / 1e12
+
+    def gain(ref, x):
+        return (ref["best_len"] - x["best_len"]) / ref["best_len"]
     return {
         "training": {"instances": 64, "n": 20000, "edges": E,
-                     "label_colony": "batched, m=64, k=16, beta=2, 30 iterations",
-                     "set_build_s": set_s,
-                     "steps": 3000, "batch": 65536, "lr": 2e-3, "train_s": tr.seconds,
-                     "loss": [[s_, l_] for s_, l_ in tr.losses]},
+                     "label_colony": "batched, m=64, k=16, beta=2, 30 iterations, best tours "
+                                     "2-optimal within 1,000 positions",
+                     "set_build_s": set_s, "steps": 3000, "batch": 65536, "lr": 2e-3,
+                     "train_s": tr.seconds, "loss": tr.losses},
         "kernels": {
             "mlp_forward": {"edges": Ev, "ms": fwd_ms, "flop_per_edge": MLP_FLOP_FORWARD,
                             "tflops": fwd_tflops, "peak_bf16_tflops": MFMA_BF16_PEAK_TFLOPS,
@@ -271,10 +430,17 @@ def learned_block(xy_eval, cfg):
             "mlp_backward": {"edges": B, "ms": bwd_ms, "flop_per_edge": MLP_FLOP_BACKWARD,
                              "tflops": bwd_tflops, "frac": bwd_tflops / MFMA_BF16_PEAK_TFLOPS},
             "edge_features": {"edges": Ev, "ms": feat_ms}},
+        "beta_selection_held_out": {"instances": "2 x n=20,000 uniform (seeds 5000, 5001), "
+                                                 "m=256, k=16, 30 iterations, mean best",
+                                    "plain": {f"{b:g}": v for b, v in sel["plain"].items()},
+                                    "learned": {f"{b:g}": v for b, v in sel["learned"].items()},
+                                    "best_beta_plain": b_plain, "best_beta_learned": b_lrn},
         "equal_wall_clock": {
-            "seconds": T, "plain_beta2": plain, "learned_beta8": lrn, "plain_beta8": plain8,
-            "gain_vs_plain": (plain["best_len"] - lrn["best_len"]) / plain["best_len"],
-            "gain_vs_plain_same_beta": (plain8["best_len"] - lrn["best_len"]) / plain8["best_len"]},
+            "seconds": T, "plain_best_beta": plain, "learned_best_beta": lrn,
+            "plain_at_learned_beta": plain_same, "plain_beta2": plain2, "learned_beta2": lrn2,
+            "gain_each_at_best_beta": gain(plain, lrn),
+            "gain_same_beta": gain(plain_same, lrn),
+            "gain_beta2": gain(plain2, lrn2)},
     }
 
 
@@ -525,6 +691,7 @@ def main():
     traffic = None if tb is None else tb / launch_s / 1e9
     ib = iter_best.cpu().numpy()
     best_len = int(col.best_len.item())
+    atomics = deposit_atomics(col)
 
     out = {
         "metric": "ant construction steps/sec at n=200K",
@@ -552,6 +719,12 @@ def main():
                      "traffic_bytes_per_launch": tb},
         "construct_ms": float(t_con.mean()),
         "update_ms": float(t_upd.mean()),
+        "deposit": {"atomics_per_launch": atomics,
+                    "atomics_per_s": atomics / (t_upd.mean() * 1e-3),
+                    "atomic_rate_probe_per_s": ATOMIC_RATE_PROBE,
+                    "frac_of_probe": atomics / (t_upd.mean() * 1e-3) / ATOMIC_RATE_PROBE,
+                    "note": "one int64 atomic per tour edge with a candidate slot (the last "
+                            "iteration's tours); update_ms also holds the merge and quanta"},
         "best_ms": float(t_best.mean()),
         "construct_ant_steps_per_s": steps_per_iter / (t_con.mean() * 1e-3),
         "setup_ms": {"candidates": t_cand * 1e3, "nn_tour_init": t_init * 1e3},
@@ -587,6 +760,9 @@ def main():
             xy, cfg, gpu_time, "local_best", 1, two_opt_p=0.001, window=500)
     if not args.no_cpu_baseline:
         threads = args.cpu_threads or max(1, min(16, os.cpu_count() or 1))
+        for name in ("c1", "c2"):
+            log(f"[bench] {name}: GPU and oracle runs to completion, {threads} threads")
+            out[f"equal_time_{name}"] = equal_time_block(name, threads)
         log(f"[bench] cpu baseline with {threads} threads")
         cb = cpu_baseline(xy, cfg, tau0_gpu, threads)
         out["cpu_baseline"] = {kk: cb[kk] for kk in ("value", "unit", "cores", "kind", "sample")}

@@ -48,6 +48,7 @@ extern "C" {
 #define ACO_ERR_DEGENERATE (-3)  /* every city coincides: the NN tour has length 0 */
 #define ACO_ERR_WORKSPACE (-4)   /* workspace smaller than the matching *_bytes query */
 #define ACO_ERR_HIP (-5)         /* a HIP runtime call failed */
+#define ACO_ERR_DEVICE (-6)      /* a kernel found device data breaking a stated precondition */
 
 #define ACO_COORD_LIMIT 536870911 /* 2^29 - 1: every distance fits in int32 */
 #define ACO_MAX_K 64               /* one candidate per lane of a 64-wide wavefront */
@@ -58,6 +59,41 @@ const char *aco_strerror(int code);
 const char *aco_last_error(void);
 /* Library version string. */
 const char *aco_version(void);
+
+/* Device-side checks.  Some preconditions depend on device data the host does
+ * not read before a launch (a local best that is not a permutation, a tour
+ * entry out of range, a tour length <= 0, ...).  A kernel
+ * that meets one keeps every access in range, finishes normally and sets a
+ * bit in the current device's error word (one word per device, shared by all
+ * streams and threads).  Every entry point that synchronises reports and
+ * clears it after its own work: ACO_ERR_DEVICE, with aco_last_error() naming
+ * the checks that failed.  Results written since the first failure are not
+ * to be trusted.
+ *
+ * aco_device_error: synchronises with `stream` and reports the word as
+ * above (ACO_OK when no check failed since the last report).  Errors: DEVICE,
+ * HIP. */
+int aco_device_error(void *stream);
+
+/* One query for the workspace of any entry point that takes one (each also
+ * has its own query below):
+ *   ACO_WS_GRID        aco_grid_bytes(n)
+ *   ACO_WS_CONSTRUCT   aco_construct_workspace_bytes(n, k)
+ *   ACO_WS_UPDATE      aco_update_workspace_bytes(n, k, m)
+ *   ACO_WS_RUN         aco_run_workspace_bytes(n, {m, k, eta = 1/d})
+ *   ACO_WS_TWO_OPT     aco_two_opt_workspace_bytes(n, m, 1)
+ *   ACO_WS_FEATURES    aco_features_workspace_bytes()
+ *   ACO_WS_MLP_BACKWARD aco_mlp_backward_workspace_bytes(n * k edges)
+ * Returns 0 for an unknown `which` or sizes the query refuses.  (The batched
+ * workspace depends on every instance's size: aco_batch_workspace_bytes.) */
+#define ACO_WS_GRID 0
+#define ACO_WS_CONSTRUCT 1
+#define ACO_WS_UPDATE 2
+#define ACO_WS_RUN 3
+#define ACO_WS_TWO_OPT 4
+#define ACO_WS_FEATURES 5
+#define ACO_WS_MLP_BACKWARD 6
+size_t aco_workspace_bytes(int32_t which, int32_t n, int32_t k, int32_t m);
 
 /* ------------------------------------------------------------------------
  * Candidate lists and spatial grid.
@@ -94,8 +130,9 @@ int aco_build_candidates(const int32_t *xy, int32_t n, int32_t k, double beta, c
  *             block are used as scratch for the tour length)
  *   nn_tour   int32 [n] (output)   tau float [n][k] (output)
  *   tau0_out  host float* (output, may be NULL); L_nn_out host int64* (may be NULL)
- * Synchronises.  Errors: INVALID_ARG, DEGENERATE (L_nn == 0), UNSUPPORTED
- * (visited bitmask of ceil(n/32) words does not fit in LDS).
+ * Synchronises (and reports device checks, see aco_device_error).
+ * Errors: INVALID_ARG, DEGENERATE (L_nn == 0), UNSUPPORTED (visited bitmask
+ * of ceil(n/32) words does not fit in LDS), DEVICE.
  * ------------------------------------------------------------------------ */
 int aco_init_pheromone(const int32_t *xy, int32_t n, int32_t k, const int32_t *nn,
                        const int32_t *nnd, void *grid, int32_t *nn_tour, float *tau,
@@ -141,12 +178,16 @@ int aco_construct_tours(const int32_t *xy, int32_t n, int32_t k, const int32_t *
  * and the merge is tau = fl32(tau' + fl32(acc) * 2^-deposit_shift).
  *
  *   tours int32 [m][n] (any permutations), slots uint8 [m][n]: the record
- *   aco_construct_tours wrote for exactly these tours (trusted, only range
- *   checked), or NULL (then every edge is located by scanning the candidate
- *   rows), lengths int64 [m] > 0, 0 < rho <= 1,
- *   0 <= deposit_shift <= 62 (the caller keeps m * 2^shift / min L < 2^63),
+ *   aco_construct_tours wrote for exactly these tours (trusted: a record of
+ *   other tours gives wrong pheromone, unreported; checking it would cost a
+ *   gather per edge), or NULL (then every edge is located by scanning the
+ *   candidate rows), lengths int64 [m] > 0,
+ *   0 < rho <= 1, 0 <= deposit_shift <= 62 (m * floor(2^shift / L) < 2^63
+ *   for every length L keeps the int64 sums exact),
  *   tau float [n][k] (in/out), ws: aco_update_workspace_bytes(n, k, m) bytes.
- * Errors: INVALID_ARG, WORKSPACE.
+ * Errors: INVALID_ARG, WORKSPACE.  Device checks (ACO_ERR_DEVICE, see
+ * aco_device_error): a tour entry out of range (that edge is skipped), a
+ * length <= 0 (its deposit is 0) or a quantum with m * q >= 2^63.
  * ------------------------------------------------------------------------ */
 size_t aco_update_workspace_bytes(int32_t n, int32_t k, int32_t m);
 int aco_update_pheromone(int32_t n, int32_t k, const int32_t *nn, const int8_t *rev, int32_t m,
@@ -171,22 +212,37 @@ int aco_track_best(int32_t n, int32_t m, const int32_t *tours, const int64_t *le
  * construction (iteration t uses the pheromone after t updates), update and
  * best tracking.
  * ------------------------------------------------------------------------ */
+#define ACO_ETA_DISTANCE 0 /* eta = 1/d (Section 2) */
+#define ACO_ETA_LEARNED 1  /* eta = sigmoid of the edge-scoring network's score (below) */
+
 typedef struct aco_params {
+    uint32_t struct_size;  /* sizeof(aco_params_t) as the caller was built (see below) */
     int32_t m;             /* ants per iteration, >= 1 */
-    int32_t k;             /* candidates per city */
+    int32_t k;             /* candidates per city (0: k-auto, aco_run_batched only) */
     double alpha;          /* pheromone exponent, >= 0 */
     double beta;           /* heuristic exponent, >= 0 */
     double rho;            /* evaporation rate, 0 < rho <= 1 */
     int32_t iterations;    /* >= 0 */
     int32_t deposit_shift; /* fixed-point fraction bits of the deposit, 0..62 (32) */
     uint64_t seed;         /* Philox key */
+    int32_t eta_mode;      /* ACO_ETA_DISTANCE (default) or ACO_ETA_LEARNED (aco_run only) */
+    const float *mlp_w;    /* ACO_ETA_LEARNED: device FP32 [ACO_MLP_PARAMS] network parameters */
 } aco_params_t;
+/* The library reads only the caller's struct_size bytes; later fields take
+ * their defaults (eta_mode ACO_ETA_DISTANCE, mlp_w NULL).  struct_size must
+ * cover the fields through seed (INVALID_ARG otherwise).  The batched entry
+ * points refuse ACO_ETA_LEARNED (UNSUPPORTED). */
 
 size_t aco_run_workspace_bytes(int32_t n, const aco_params_t *p);
 /*   best_tour int32 [n], best_len int64 [1] (outputs, device)
  *   iter_best int64 [iterations] (output, may be NULL)
  *   tau_out   float [n][k] final pheromone (output, may be NULL)
- * Synchronises (during set-up).  Errors: as the steps above. */
+ * With ACO_ETA_LEARNED the candidate edges' features (aco_edge_features) go
+ * through the network (aco_mlp_forward) right after the candidate build, and
+ * eta_b = sigmoid(z)^beta replaces (1/d)^beta; the workspace then also holds
+ * the features (32 bytes per candidate slot).
+ * Synchronises (during set-up).  Errors: as the steps above; INVALID_ARG for
+ * an unknown eta_mode or ACO_ETA_LEARNED without mlp_w. */
 int aco_run(const int32_t *xy, int32_t n, const aco_params_t *p, int32_t *best_tour,
             int64_t *best_len, int64_t *iter_best, float *tau_out, void *ws, size_t ws_bytes,
             void *stream);
@@ -207,7 +263,8 @@ int aco_run(const int32_t *xy, int32_t n, const aco_params_t *p, int32_t *best_t
  *
  * aco_batch_setup builds every instance's grid, candidate lists and
  * nearest-neighbour tour (the best so far starts as that tour) and
- * synchronises to report INVALID_ARG / DEGENERATE.  aco_batch_iterate then
+ * synchronises to report INVALID_ARG / DEGENERATE (and device checks, see
+ * aco_device_error).  aco_batch_iterate then
  * runs iterations first .. first+count-1 of every instance in ONE persistent
  * kernel launch (no allocation, no host synchronisation: it can be captured in
  * a HIP graph); its iter_best is [B][count].  `waves` = waves per instance
@@ -218,10 +275,24 @@ int aco_run(const int32_t *xy, int32_t n, const aco_params_t *p, int32_t *best_t
  * for the tuned value (before tuning: four ants per wave with the most waves
  * the LDS holds when k <= 16, else 8 waves, bits, 4 per SIMD), change the
  * speed, never the results.  aco_run_batched
- * = set-up + all iterations; with autotune != 0 its first iterations each run
- * a different configuration, timed, and the fastest (cached per device and
- * shape) runs the rest; tuned_out (host int32 [3], may be NULL) receives
- * {waves, layout, occupancy}.
+ * = set-up + all iterations.  With autotune != 0 every candidate shape runs
+ * iteration 0 from the state the set-up left (restored before each, timed),
+ * then the state is restored and all iterations run in the fastest shape
+ * (cached per device and shape; the results equal those of any fixed shape).
+ * With p->k == 0 (k-auto, aco_run_batched only) the candidate counts 8, 10,
+ * 12 and 16 (those <= min n_b - 1) each run the set-up and min(iterations, 8)
+ * iterations; a candidate's quality after i iterations is the mean over
+ * instances of best-so-far / NN-tour length; the target is the worst final
+ * quality among them, and the k that reaches it in the least time (iterations
+ * times its time per iteration; ties to the smaller k) is set up afresh and
+ * runs all iterations.  tuned_out (host int32 [4], may be NULL) receives
+ * {waves, layout, occupancy, k}.  The tuning steps allocate stream-ordered
+ * scratch (hipMallocAsync) and free it before the run.
+ * aco_batch_workspace_bytes with k = 0 sizes for the largest candidate.
+ * step_prob (aco_batch_iterate; float, laid out as the tours, may be NULL)
+ * receives the probability of every move of the last iteration run, as
+ * aco_construct_tours' step_prob; it needs one ant per wave (an explicit
+ * ACO_VIS_BITS_X4 is refused, the default shape falls back to bits).
  * aco_batch_layout gives the byte offsets of the state arrays inside ws
  * (for inspection: nn/nnd/rev/eta_b/tau are [N][k], tours/slots are instance
  * b at m*offsets[b] as [m][n_b], lengths [B][m]).
@@ -243,8 +314,8 @@ int aco_batch_setup(const int32_t *xy, const int64_t *offsets, int32_t B, const 
 int aco_batch_iterate(const int32_t *xy, const int64_t *offsets, int32_t B,
                       const aco_params_t *p, int32_t first_iteration, int32_t count,
                       int32_t waves, int32_t vis_layout, int32_t occupancy, int32_t *best_tours,
-                      int64_t *best_lens, int64_t *iter_best, void *ws, size_t ws_bytes,
-                      void *stream);
+                      int64_t *best_lens, int64_t *iter_best, float *step_prob, void *ws,
+                      size_t ws_bytes, void *stream);
 int aco_run_batched(const int32_t *xy, const int64_t *offsets, int32_t B, const aco_params_t *p,
                     int32_t autotune, int32_t *best_tours, int64_t *best_lens,
                     int64_t *iter_best, void *ws, size_t ws_bytes, void *stream,
@@ -295,7 +366,13 @@ int aco_construct_partial(const int32_t *xy, int32_t n, int32_t k, const int32_t
  *           every local best (as aco_update_local_best keeps it): the kept
  *           part's length is then that length minus the edges outside the
  *           kept part, instead of a sum over the kept part (same result when
- *           the lengths are exact; a wrong length gives a wrong tour length).
+ *           the lengths are exact).  A length that no tour of n cities can
+ *           have (<= 0, or >= n 2^31, such as the INT64_MAX start value) trips
+ *           a device check (ACO_ERR_DEVICE) and that ant's kept part is
+ *           summed edge by edge; so does a result that comes out <= 0.  Any
+ *           other wrong length gives a wrong tour length, unreported.
+ *   Device checks (ACO_ERR_DEVICE, see aco_device_error): an lbest row that
+ *   is not a permutation of 0..n-1 (out-of-range entries are read as city 0).
  * opts is a host pointer (NULL: roulette, full tours).  Other arguments and
  * errors as aco_construct_tours; Independent Roulette also keeps one block of
  * uniforms in LDS (64 steps x k rounded up to 4 words), so UNSUPPORTED is
@@ -303,12 +380,16 @@ int aco_construct_partial(const int32_t *xy, int32_t n, int32_t k, const int32_t
 #define ACO_SAMPLER_ROULETTE 0
 #define ACO_SAMPLER_INDEPENDENT 1
 typedef struct aco_construct_opts {
+    uint32_t struct_size;       /* sizeof(aco_construct_opts_t) as the caller was built */
     int32_t sampler;
     double p_partial;
     int32_t max_modify;
     const int32_t *lbest;
     const int64_t *lbest_len;   /* [m] or NULL (see above) */
 } aco_construct_opts_t;
+/* struct_size lets the struct grow: the library reads only the caller's
+ * struct_size bytes and gives later fields their defaults (lbest_len NULL).
+ * It must cover at least the fields through lbest (INVALID_ARG otherwise). */
 
 int aco_construct_ex(const int32_t *xy, int32_t n, int32_t k, const int32_t *nn,
                      const int32_t *nnd, const float *eta_b, const void *grid, const float *tau,
@@ -334,8 +415,11 @@ int aco_update_local_best(int32_t n, int32_t m, const int32_t *tours, const int6
  * fl32(delta * 2^-shift))), both directed slots of an edge equal.
  *   lbest int32 [m][n], lbest_len int64 [m] (> 0); tau float [n][k] (output)
  *   ws  aco_update_workspace_bytes(n, k, m) bytes
- * Errors: INVALID_ARG (sizes, shift outside [0, 62], tau_base or delta < 0 or
- * not finite), WORKSPACE. */
+ * Every quantum is at most 2^shift and a slot sums at most m of them, so
+ * m * 2^shift must stay below 2^63.
+ * Errors: INVALID_ARG (sizes, shift outside [0, 62] or m * 2^shift >= 2^63,
+ * tau_base or delta < 0 or not finite), WORKSPACE.  Device checks: a length
+ * <= 0 (quantum 0), a tour entry out of range (edge skipped). */
 int aco_pheromone_local_best(int32_t n, int32_t k, const int32_t *nn, const int8_t *rev,
                              int32_t m, const int32_t *lbest, const int64_t *lbest_len,
                              double tau_base, double delta, int32_t deposit_shift, float *tau,
@@ -387,8 +471,9 @@ size_t aco_two_opt_workspace_bytes(int32_t n, int32_t m, int32_t batch);
  *   stats    host pointer or NULL
  *   ws       aco_two_opt_workspace_bytes(n, m, batch) bytes, batch >= 1
  * Synchronises with `stream` once per call plus once per 16 rounds (the host
- * reads how many moves each round applied).
- * Errors: INVALID_ARG (sizes, window, p, NULL pointers), WORKSPACE, HIP. */
+ * reads how many moves each round applied), and reports device checks (see
+ * aco_device_error).
+ * Errors: INVALID_ARG (sizes, window, p, NULL pointers), WORKSPACE, HIP, DEVICE. */
 int aco_two_opt(const int32_t *xy, int32_t n, int32_t m, int32_t *tours, int64_t *lengths,
                 uint8_t *slots, int32_t window, double p, uint64_t seed, int64_t iteration,
                 int64_t max_rounds, int32_t batch, aco_two_opt_stats_t *stats, void *ws,

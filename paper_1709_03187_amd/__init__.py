@@ -26,12 +26,14 @@ ACO_ERR_UNSUPPORTED = -2
 ACO_ERR_DEGENERATE = -3
 ACO_ERR_WORKSPACE = -4
 ACO_ERR_HIP = -5
+ACO_ERR_DEVICE = -6
 ACO_COORD_LIMIT = 2**29 - 1
 ACO_MAX_K = 64
 NO_SLOT = 255
 
 EXPORTS = (
-    "aco_strerror", "aco_last_error", "aco_version", "aco_grid_bytes", "aco_build_candidates",
+    "aco_strerror", "aco_last_error", "aco_version", "aco_device_error", "aco_grid_bytes",
+    "aco_build_candidates",
     "aco_init_pheromone", "aco_construct_workspace_bytes", "aco_construct_tours",
     "aco_update_workspace_bytes", "aco_update_pheromone", "aco_track_best",
     "aco_run_workspace_bytes", "aco_run", "aco_batch_workspace_bytes", "aco_batch_layout",
@@ -39,14 +41,18 @@ EXPORTS = (
     "aco_edge_features", "aco_mlp_forward", "aco_mlp_backward_workspace_bytes",
     "aco_mlp_backward", "aco_mlp_adam", "aco_tour_edge_labels", "aco_construct_partial",
     "aco_update_local_best", "aco_pheromone_local_best", "aco_construct_ex",
-    "aco_two_opt_workspace_bytes", "aco_two_opt",
+    "aco_two_opt_workspace_bytes", "aco_two_opt", "aco_workspace_bytes",
 )
+ACO_WS_GRID, ACO_WS_CONSTRUCT, ACO_WS_UPDATE, ACO_WS_RUN = 0, 1, 2, 3
+ACO_WS_TWO_OPT, ACO_WS_FEATURES, ACO_WS_MLP_BACKWARD = 4, 5, 6
 ACO_TWO_OPT_MAX_WINDOW = 2048
 ACO_SAMPLER_ROULETTE = 0
 ACO_SAMPLER_INDEPENDENT = 1
 ACO_MLP_PARAMS = 4801
 ACO_MLP_OUT_LOGIT = 0
 ACO_MLP_OUT_ETA_B = 1
+ACO_ETA_DISTANCE = 0
+ACO_ETA_LEARNED = 1
 ACO_VIS_BITS = 1
 ACO_VIS_BYTES = 2
 ACO_VIS_BITS_X4 = 3
@@ -59,14 +65,21 @@ class AcoError(RuntimeError):
 
 
 class AcoParams(C.Structure):
-    _fields_ = [("m", C.c_int32), ("k", C.c_int32), ("alpha", C.c_double),
-                ("beta", C.c_double), ("rho", C.c_double), ("iterations", C.c_int32),
-                ("deposit_shift", C.c_int32), ("seed", C.c_uint64)]
+    _fields_ = [("struct_size", C.c_uint32), ("m", C.c_int32), ("k", C.c_int32),
+                ("alpha", C.c_double), ("beta", C.c_double), ("rho", C.c_double),
+                ("iterations", C.c_int32), ("deposit_shift", C.c_int32), ("seed", C.c_uint64),
+                ("eta_mode", C.c_int32), ("mlp_w", C.c_void_p)]
+
+    def __init__(self, *args, **kw):
+        super().__init__(C.sizeof(AcoParams), *args, **kw)
 
 
 class AcoConstructOpts(C.Structure):
-    _fields_ = [("sampler", C.c_int32), ("p_partial", C.c_double), ("max_modify", C.c_int32),
-                ("lbest", C.c_void_p), ("lbest_len", C.c_void_p)]
+    _fields_ = [("struct_size", C.c_uint32), ("sampler", C.c_int32), ("p_partial", C.c_double),
+                ("max_modify", C.c_int32), ("lbest", C.c_void_p), ("lbest_len", C.c_void_p)]
+
+    def __init__(self, *args, **kw):
+        super().__init__(C.sizeof(AcoConstructOpts), *args, **kw)
 
 
 class AcoTwoOptStats(C.Structure):
@@ -93,7 +106,9 @@ def lib():
             "aco_strerror": (C.c_char_p, [C.c_int]),
             "aco_last_error": (C.c_char_p, []),
             "aco_version": (C.c_char_p, []),
+            "aco_device_error": (C.c_int, [p]),
             "aco_grid_bytes": (sz, [i32]),
+            "aco_workspace_bytes": (sz, [i32, i32, i32, i32]),
             "aco_build_candidates": (C.c_int, [p, i32, i32, dbl, p, p, p, p, p, p, sz, p]),
             "aco_init_pheromone": (C.c_int, [p, i32, i32, p, p, p, p, p, p, p, p]),
             "aco_construct_workspace_bytes": (sz, [i32, i32]),
@@ -110,7 +125,7 @@ def lib():
                                            C.POINTER(AcoBatchLayout)]),
             "aco_batch_setup": (C.c_int, [p, p, i32, C.POINTER(AcoParams), p, p, p, sz, p]),
             "aco_batch_iterate": (C.c_int, [p, p, i32, C.POINTER(AcoParams), i32, i32, i32, i32,
-                                            i32, p, p, p, p, sz, p]),
+                                            i32, p, p, p, p, p, sz, p]),
             "aco_run_batched": (C.c_int, [p, p, i32, C.POINTER(AcoParams), i32, p, p, p, p, sz,
                                           p, p]),
             "aco_features_workspace_bytes": (sz, []),
@@ -172,6 +187,16 @@ def _t():
 # ------------------------------------------------------------ entry points
 def aco_version() -> str:
     return lib().aco_version().decode()
+
+
+def aco_device_error(stream=None):
+    """Synchronise and raise AcoError (ACO_ERR_DEVICE) if a kernel's device-side
+    check failed since the last report."""
+    _check(lib().aco_device_error(_stream(stream)))
+
+
+def aco_workspace_bytes(which: int, n: int, k: int, m: int) -> int:
+    return int(lib().aco_workspace_bytes(int(which), int(n), int(k), int(m)))
 
 
 def aco_grid_bytes(n: int) -> int:
@@ -542,29 +567,30 @@ def aco_batch_setup(xy, offsets, B, params, best_tours, best_lens, ws, stream=No
 
 
 def aco_batch_iterate(xy, offsets, B, params, first_iteration, count, waves, vis_layout,
-                      occupancy, best_tours, best_lens, iter_best, ws, stream=None):
+                      occupancy, best_tours, best_lens, iter_best, ws, stream=None,
+                      step_prob=None):
     torch = _t()
     arr, ptr = _host_i64(offsets)
     _check(lib().aco_batch_iterate(
         _ptr(xy, torch.int32, "xy"), ptr, B, C.byref(params), int(first_iteration), int(count),
         int(waves), int(vis_layout), int(occupancy),
         _ptr(best_tours, torch.int32, "best_tours"), _ptr(best_lens, torch.int64, "best_lens"),
-        _ptr(iter_best, torch.int64, "iter_best"), _ptr(ws, torch.uint8, "ws"), ws.numel(),
-        _stream(stream)))
+        _ptr(iter_best, torch.int64, "iter_best"), _ptr(step_prob, torch.float32, "step_prob"),
+        _ptr(ws, torch.uint8, "ws"), ws.numel(), _stream(stream)))
 
 
 def aco_run_batched(xy, offsets, B, params, autotune, best_tours, best_lens, iter_best, ws,
                     stream=None):
-    """Returns the (waves, layout) configuration used."""
+    """Returns the launch shape and k used: (waves, layout, occupancy, k)."""
     torch = _t()
     arr, ptr = _host_i64(offsets)
-    tuned = (C.c_int32 * 3)()
+    tuned = (C.c_int32 * 4)()
     _check(lib().aco_run_batched(
         _ptr(xy, torch.int32, "xy"), ptr, B, C.byref(params), int(autotune),
         _ptr(best_tours, torch.int32, "best_tours"), _ptr(best_lens, torch.int64, "best_lens"),
         _ptr(iter_best, torch.int64, "iter_best"), _ptr(ws, torch.uint8, "ws"), ws.numel(),
         _stream(stream), tuned))
-    return int(tuned[0]), int(tuned[1]), int(tuned[2])
+    return int(tuned[0]), int(tuned[1]), int(tuned[2]), int(tuned[3])
 
 
 class Batch:
@@ -584,20 +610,28 @@ class Batch:
                               dtype=torch.uint8, device=device)
         self.best_tours = torch.empty(self.N, dtype=torch.int32, device=device)
         self.best_lens = torch.empty(self.B, dtype=torch.int64, device=device)
-        self.layout = aco_batch_layout(self.offsets, self.B, self.params)
+        # k = 0 (k-auto, run() only): the layout is known once run() has chosen k
+        self.layout = aco_batch_layout(self.offsets, self.B, self.params) if k > 0 else None
 
     def setup(self, stream=None):
         aco_batch_setup(self.xy, self.offsets, self.B, self.params, self.best_tours,
                         self.best_lens, self.ws, stream)
 
-    def iterate(self, first, count, waves=0, layout=0, iter_best=None, stream=None, occupancy=0):
+    def iterate(self, first, count, waves=0, layout=0, iter_best=None, stream=None, occupancy=0,
+                step_prob=None):
         aco_batch_iterate(self.xy, self.offsets, self.B, self.params, first, count, waves, layout,
-                          occupancy,
-                          self.best_tours, self.best_lens, iter_best, self.ws, stream)
+                          occupancy, self.best_tours, self.best_lens, iter_best, self.ws, stream,
+                          step_prob=step_prob)
 
     def run(self, autotune=1, iter_best=None, stream=None):
-        return aco_run_batched(self.xy, self.offsets, self.B, self.params, autotune,
-                               self.best_tours, self.best_lens, iter_best, self.ws, stream)
+        """Set-up and all iterations; returns (waves, layout, occupancy, k).  With
+        k = 0 the chosen k is kept in params and the state views follow it."""
+        tuned = aco_run_batched(self.xy, self.offsets, self.B, self.params, autotune,
+                                self.best_tours, self.best_lens, iter_best, self.ws, stream)
+        if self.params.k == 0:
+            self.params.k = tuned[3]
+            self.layout = aco_batch_layout(self.offsets, self.B, self.params)
+        return tuned
 
     def view(self, name, dtype, count):
         """A tensor view of one state array inside the workspace."""

@@ -34,15 +34,22 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source to an object, then link libaco.so (always rebuilds)."""
+STEP_PROFILE_OUT = os.path.join(PKG, "libaco_step_profile.so")
+
+
+def build(verbose: bool = False, step_profile: bool = False) -> str:
+    """Compile every source to an object, then link libaco.so (always rebuilds).
+    step_profile: build libaco_step_profile.so instead, whose construction
+    kernels also record per-ant clock counters (see step_profile.py)."""
     cc = hipcc()
-    bdir = os.path.join(PKG, "_build")
+    bdir = os.path.join(PKG, "_build_step_profile" if step_profile else "_build")
+    out = STEP_PROFILE_OUT if step_profile else OUT
+    extra = ["-DACO_STEP_PROFILE"] if step_profile else []
     os.makedirs(bdir, exist_ok=True)
 
     def compile_one(src):
         obj = os.path.join(bdir, src.replace(".hip", ".o"))
-        cmd = [cc, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [cc, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True, cwd=bdir)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
@@ -55,14 +62,14 @@ def build(verbose: bool = False) -> str:
 
     with ThreadPoolExecutor(max_workers=min(4, os.cpu_count() or 1)) as ex:
         objs = list(ex.map(compile_one, SOURCES))
-    tmp = OUT + f".tmp{os.getpid()}"
+    tmp = out + f".tmp{os.getpid()}"
     cmd = [cc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True, cwd=bdir)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, OUT)
-    return OUT
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, step_profile="--step-profile" in sys.argv[1:]))

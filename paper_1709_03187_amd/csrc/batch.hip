@@ -50,6 +50,7 @@ struct BatchState {
     int64_t *lengths;      // [B][m]
     int32_t *inst_of;      // [N]
     int32_t *flag;         // bit 0: coordinate out of range, bit 1: degenerate instance
+    uint32_t *err;         // the device's error word (guards)
     int32_t B, k, m;
 };
 
@@ -247,7 +248,7 @@ __global__ __launch_bounds__(kWave) void k_b_init(BatchState S, double alpha,
     const int64_t off = S.off[b];
     const int32_t n = (int32_t)(S.off[b + 1] - off);
     const int64_t L = nn_tour_wave(S.xy + 2 * off, n, k, S.nn + off * k, S.nnd + off * k,
-                                   batch_grid(S, b), VisBits{vis}, best_tours + off);
+                                   batch_grid(S, b), VisBits{vis}, best_tours + off, S.err);
     if (L <= 0) {
         if (lane == 0) atomicOr(S.flag, 2);
         return;
@@ -277,6 +278,7 @@ struct ColonyParams {
     int64_t *best_lens;  // [B]
     int64_t *iter_best;  // row b at iter_best + b * ib_stride, or nullptr
     int32_t ib_stride;
+    float *step_prob;    // [N * m] as tours (one ant per wave only), or nullptr
 };
 
 __device__ __forceinline__ int64_t wave_sum_i64(int64_t v)
@@ -346,6 +348,7 @@ __global__ __launch_bounds__(1024, OCC) void k_b_colony(BatchState S, ColonyPara
                 T4.seed = P.seed;
                 T4.tours = tours;
                 T4.slots = slots;
+                T4.err = S.err;
                 build_ants4(T4, mine, P.set_bytes, [&]() { return batch_grid(S, b); });
             }
         } else
@@ -360,7 +363,8 @@ __global__ __launch_bounds__(1024, OCC) void k_b_colony(BatchState S, ColonyPara
             T.seed = P.seed;
             T.tour = tours + (int64_t)a * n;
             T.slots = slots + (int64_t)a * n;
-            T.prob = nullptr;
+            T.prob = P.step_prob ? P.step_prob + off * m + (int64_t)a * n : nullptr;
+            T.err = S.err;
             build_ant<KP>(T, vis, [&]() { return batch_grid(S, b); });
         }
         __syncthreads();
@@ -515,6 +519,7 @@ static BatchState batch_state(void *ws, const BatchLayoutHost &L, const int32_t 
     S.lengths = (int64_t *)(w + L.lengths);
     S.inst_of = (int32_t *)(w + L.inst_of);
     S.flag = (int32_t *)(w + L.flag);
+    S.err = device_error_word();
     S.B = B;
     S.k = k;
     S.m = m;
@@ -524,6 +529,8 @@ static BatchState batch_state(void *ws, const BatchLayoutHost &L, const int32_t 
 static int validate_batch(const int64_t *offs, int32_t B, const aco_params_t *p)
 {
     ACO_REQUIRE(p != nullptr && offs != nullptr, "NULL params or offsets");
+    if (p->eta_mode != ACO_ETA_DISTANCE)
+        return fail(ACO_ERR_UNSUPPORTED, "the batched colonies use eta = 1/d only");
     ACO_REQUIRE(B >= 1 && B <= (1 << 24), "B = %d out of range", B);
     ACO_REQUIRE(offs[0] == 0, "offsets[0] must be 0");
     int64_t nmin = INT64_MAX, nmax = 0;
@@ -608,7 +615,8 @@ static std::map<std::tuple<int, int, int, int64_t, int>, Tuning> g_tuned;
 
 static int launch_colony(const BatchState &S0, const BatchLayoutHost &L, const aco_params_t *p,
                          int32_t first, int32_t count, Tuning cfg, int32_t *best_tours,
-                         int64_t *best_lens, int64_t *iter_best, int32_t ib_stride, hipStream_t st)
+                         int64_t *best_lens, int64_t *iter_best, int32_t ib_stride, hipStream_t st,
+                         float *step_prob = nullptr)
 {
     if (S0.xy == nullptr || best_tours == nullptr || best_lens == nullptr)
         return fail(ACO_ERR_INVALID_ARG, "NULL coordinates or outputs for the colony launch");
@@ -634,6 +642,7 @@ static int launch_colony(const BatchState &S0, const BatchLayoutHost &L, const a
     P.best_lens = best_lens;
     P.iter_best = iter_best;
     P.ib_stride = ib_stride;
+    P.step_prob = step_prob;
     kern<<<S0.B, waves * kWave, lds, st>>>(S0, P);
     ACO_LAUNCH_CHECK("k_b_colony");
     return ACO_OK;
@@ -643,20 +652,38 @@ static int launch_colony(const BatchState &S0, const BatchLayoutHost &L, const a
 
 using namespace aco;
 
+// Candidate counts the k-auto mode compares (those <= min n_b - 1).
+static const int kAutoK[] = {8, 10, 12, 16};
+static constexpr int kAutoKMax = 16;
+static constexpr int kAutoProbe = 8;   // iterations each candidate runs
+
 extern "C" size_t aco_batch_workspace_bytes(const int64_t *offsets, int32_t B,
-                                            const aco_params_t *p)
+                                            const aco_params_t *pin)
 {
-    if (!offsets || !p || B < 1 || p->k < 1 || p->m < 1) return 0;
+    aco_params_t q;
+    if (load_params(pin, q) != ACO_OK) return 0;
+    const aco_params_t *p = &q;
+    if (!offsets || B < 1 || p->k < 0 || p->m < 1) return 0;
+    int k = p->k;
+    if (k == 0) {   // k-auto: room for the largest candidate
+        int64_t nmin = INT64_MAX;
+        for (int b = 0; b < B; ++b) nmin = std::min(nmin, offsets[b + 1] - offsets[b]);
+        k = (int)std::max<int64_t>(1, std::min<int64_t>(kAutoKMax, nmin - 1));
+    }
     BatchLayoutHost L;
-    batch_layout(offsets, B, p->k, p->m, L);
+    batch_layout(offsets, B, k, p->m, L);
     return L.total;
 }
 
-extern "C" int aco_batch_layout(const int64_t *offsets, int32_t B, const aco_params_t *p,
+extern "C" int aco_batch_layout(const int64_t *offsets, int32_t B, const aco_params_t *pin,
                                 aco_batch_layout_t *out)
 {
     clear_error();
-    int rc = validate_batch(offsets, B, p);
+    aco_params_t q;
+    int rc = load_params(pin, q);
+    if (rc != ACO_OK) return rc;
+    const aco_params_t *p = &q;
+    rc = validate_batch(offsets, B, p);
     if (rc != ACO_OK) return rc;
     ACO_REQUIRE(out != nullptr, "NULL output");
     BatchLayoutHost L;
@@ -674,11 +701,15 @@ extern "C" int aco_batch_layout(const int64_t *offsets, int32_t B, const aco_par
 }
 
 extern "C" int aco_batch_setup(const int32_t *xy, const int64_t *offsets, int32_t B,
-                               const aco_params_t *p, int32_t *best_tours, int64_t *best_lens,
+                               const aco_params_t *pin, int32_t *best_tours, int64_t *best_lens,
                                void *ws, size_t ws_bytes, void *stream)
 {
     clear_error();
-    int rc = validate_batch(offsets, B, p);
+    aco_params_t q;
+    int rc = load_params(pin, q);
+    if (rc != ACO_OK) return rc;
+    const aco_params_t *p = &q;
+    rc = validate_batch(offsets, B, p);
     if (rc != ACO_OK) return rc;
     ACO_REQUIRE(xy && best_tours && best_lens && ws, "NULL array argument");
     BatchLayoutHost L;
@@ -709,19 +740,25 @@ extern "C" int aco_batch_setup(const int32_t *xy, const int64_t *offsets, int32_
     int32_t flag = 0;
     ACO_HIP_CHECK(hipMemcpyAsync(&flag, S.flag, 4, hipMemcpyDeviceToHost, st));
     ACO_HIP_CHECK(hipStreamSynchronize(st));
+    rc = report_device_error(st);
+    if (rc != ACO_OK) return rc;
     if (flag & 1) return fail(ACO_ERR_INVALID_ARG, "a coordinate exceeds +-%d", ACO_COORD_LIMIT);
     if (flag & 2) return fail(ACO_ERR_DEGENERATE, "an instance has all its cities coincident");
     return ACO_OK;
 }
 
 extern "C" int aco_batch_iterate(const int32_t *xy, const int64_t *offsets, int32_t B,
-                                 const aco_params_t *p, int32_t first_iteration, int32_t count,
+                                 const aco_params_t *pin, int32_t first_iteration, int32_t count,
                                  int32_t waves, int32_t vis_layout, int32_t occupancy,
                                  int32_t *best_tours, int64_t *best_lens, int64_t *iter_best,
-                                 void *ws, size_t ws_bytes, void *stream)
+                                 float *step_prob, void *ws, size_t ws_bytes, void *stream)
 {
     clear_error();
-    int rc = validate_batch(offsets, B, p);
+    aco_params_t q;
+    int rc = load_params(pin, q);
+    if (rc != ACO_OK) return rc;
+    const aco_params_t *p = &q;
+    rc = validate_batch(offsets, B, p);
     if (rc != ACO_OK) return rc;
     ACO_REQUIRE(xy && best_tours && best_lens && ws, "NULL array argument");
     ACO_REQUIRE(first_iteration >= 0 && count >= 0, "bad iteration range");
@@ -734,6 +771,8 @@ extern "C" int aco_batch_iterate(const int32_t *xy, const int64_t *offsets, int3
                 "four ants per wave need k <= 16 (k = %d)", p->k);
     ACO_REQUIRE(occupancy == 0 || occupancy == 4 || occupancy == 8,
                 "occupancy must be 0 (tuned), 4 or 8 waves per SIMD");
+    ACO_REQUIRE(!step_prob || vis_layout != ACO_VIS_BITS_X4,
+                "step probabilities are recorded with one ant per wave only");
     BatchLayoutHost L;
     batch_layout(offsets, B, p->k, p->m, L);
     if (ws_bytes < L.total)
@@ -753,11 +792,179 @@ extern "C" int aco_batch_iterate(const int32_t *xy, const int64_t *offsets, int3
     // a given wave count with the default four-ant layout may not fit in LDS:
     // then one ant per wave
     if (!vis_layout && cfg.layout == ACO_VIS_BITS_X4 &&
-        colony_lds(cfg.waves, cfg.layout, L.nmax, p->m) > max_lds_per_block())
+        (step_prob || colony_lds(cfg.waves, cfg.layout, L.nmax, p->m) > max_lds_per_block()))
         cfg.layout = ACO_VIS_BITS;
     BatchState S = batch_state(ws, L, xy, B, p->k, p->m);
     return launch_colony(S, L, p, first_iteration, count, cfg, best_tours, best_lens, iter_best,
-                         count, as_stream(stream));
+                         count, as_stream(stream), step_prob);
+}
+
+// Device state that a batched iteration reads and changes: the pheromone, the
+// choice weights, the best tours and their lengths.  Held in stream-ordered
+// memory so that every tuning candidate starts from the same state.
+struct BatchSnapshot {
+    char *mem = nullptr;
+    size_t tau = 0, rows = 0, bt = 0, bl = 0, total = 0;
+};
+
+static int snapshot_alloc(BatchSnapshot &s, const BatchLayoutHost &L, int k, int B,
+                          hipStream_t st)
+{
+    s.tau = (size_t)L.N * k * 4;
+    s.rows = (size_t)L.N * k * sizeof(CandW);
+    s.bt = (size_t)L.N * 4;
+    s.bl = (size_t)B * 8;
+    s.total = s.tau + s.rows + s.bt + s.bl;
+    ACO_HIP_CHECK(hipMallocAsync((void **)&s.mem, s.total, st));
+    return ACO_OK;
+}
+
+static int snapshot_copy(const BatchSnapshot &s, const BatchState &S, int32_t *best_tours,
+                         int64_t *best_lens, bool take, hipStream_t st)
+{
+    char *m = s.mem;
+    void *dev[4] = {S.tau, S.rows, best_tours, best_lens};
+    const size_t len[4] = {s.tau, s.rows, s.bt, s.bl};
+    for (int i = 0; i < 4; ++i) {
+        if (take)
+            ACO_HIP_CHECK(hipMemcpyAsync(m, dev[i], len[i], hipMemcpyDeviceToDevice, st));
+        else
+            ACO_HIP_CHECK(hipMemcpyAsync(dev[i], m, len[i], hipMemcpyDeviceToDevice, st));
+        m += len[i];
+    }
+    return ACO_OK;
+}
+
+// Shape tuning: every candidate runs iteration 0 from the state left by the
+// set-up (restored before each), timed with events; the state is restored
+// once more at the end.  The fastest shape is cached per device and shape.
+static int tune_shape(const BatchState &S, const BatchLayoutHost &L, const aco_params_t *p,
+                      int32_t *best_tours, int64_t *best_lens, hipStream_t st, Tuning &best)
+{
+    const Tuning cand[] = {{4, ACO_VIS_BITS, 4},     {8, ACO_VIS_BITS, 4},
+                           {16, ACO_VIS_BITS, 4},    {4, ACO_VIS_BYTES, 4},
+                           {8, ACO_VIS_BYTES, 4},    {16, ACO_VIS_BYTES, 4},
+                           {4, ACO_VIS_BITS, 8},     {8, ACO_VIS_BITS, 8},
+                           {16, ACO_VIS_BITS, 8},    {8, ACO_VIS_BYTES, 8},
+                           {4, ACO_VIS_BITS_X4, 4},  {8, ACO_VIS_BITS_X4, 4},
+                           {16, ACO_VIS_BITS_X4, 4}, {4, ACO_VIS_BITS_X4, 8},
+                           {8, ACO_VIS_BITS_X4, 8},  {16, ACO_VIS_BITS_X4, 8}};
+    BatchSnapshot snap;
+    int rc = snapshot_alloc(snap, L, p->k, S.B, st);
+    if (rc != ACO_OK) return rc;
+    rc = snapshot_copy(snap, S, best_tours, best_lens, true, st);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (rc == ACO_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        rc = fail(ACO_ERR_HIP, "hipEventCreate failed");
+    float best_ms = 1e30f;
+    for (const Tuning &c : cand) {
+        if (rc != ACO_OK) break;
+        if (colony_lds(c.waves, c.layout, L.nmax, p->m) > max_lds_per_block()) continue;
+        if (c.layout == ACO_VIS_BITS_X4 && p->k > 16) continue;
+        rc = snapshot_copy(snap, S, best_tours, best_lens, false, st);
+        if (rc != ACO_OK) break;
+        if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(ACO_ERR_HIP, "event"); break; }
+        rc = launch_colony(S, L, p, 0, 1, c, best_tours, best_lens, nullptr, 1, st);
+        if (rc != ACO_OK) break;
+        float ms = 0;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = fail(ACO_ERR_HIP, "timing a tuning candidate failed");
+            break;
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    if (rc == ACO_OK) rc = snapshot_copy(snap, S, best_tours, best_lens, false, st);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    const hipError_t fe = hipFreeAsync(snap.mem, st);
+    if (rc == ACO_OK && fe != hipSuccess) rc = fail(ACO_ERR_HIP, "hipFreeAsync failed");
+    return rc;
+}
+
+// k-auto: every candidate k runs the set-up and min(iterations, 8)
+// iterations; its quality after i iterations is the mean over instances of
+// (best so far, the NN tour included) / (NN-tour length), which does not
+// depend on k.  The target is the worst final quality among the candidates,
+// which every candidate reaches; the chosen k reaches it in the least time
+// (iterations needed times its measured time per iteration; ties to the
+// smaller k).
+static int choose_k(const int32_t *xy, const int64_t *offsets, int32_t B, const aco_params_t *p,
+                    int32_t *best_tours, int64_t *best_lens, void *ws, size_t ws_bytes,
+                    void *stream, int &k_out)
+{
+    hipStream_t st = as_stream(stream);
+    int64_t nmin = INT64_MAX;
+    for (int b = 0; b < B; ++b) nmin = std::min(nmin, offsets[b + 1] - offsets[b]);
+    const int P = std::max(1, std::min(p->iterations, kAutoProbe));
+    std::vector<int> ks;
+    for (int k : kAutoK)
+        if (k <= nmin - 1) ks.push_back(k);
+    if (ks.empty()) ks.push_back((int)std::max<int64_t>(1, std::min<int64_t>(nmin - 1, kAutoKMax)));
+    std::vector<std::vector<double>> quality(ks.size(), std::vector<double>(P));
+    std::vector<double> per_iter_ms(ks.size());
+    int64_t *ib = nullptr;
+    ACO_HIP_CHECK(hipMallocAsync((void **)&ib, (size_t)B * P * 8, st));
+    std::vector<int64_t> L0(B), hib((size_t)B * P);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = ACO_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        rc = fail(ACO_ERR_HIP, "hipEventCreate failed");
+    for (size_t c = 0; c < ks.size() && rc == ACO_OK; ++c) {
+        aco_params_t q = *p;
+        q.k = ks[c];
+        q.iterations = P;
+        rc = aco_batch_setup(xy, offsets, B, &q, best_tours, best_lens, ws, ws_bytes, stream);
+        if (rc != ACO_OK) break;
+        if (hipMemcpyAsync(L0.data(), best_lens, (size_t)B * 8, hipMemcpyDeviceToHost, st) !=
+            hipSuccess) { rc = fail(ACO_ERR_HIP, "copy"); break; }
+        BatchLayoutHost L;
+        batch_layout(offsets, B, q.k, q.m, L);
+        const BatchState S = batch_state(ws, L, xy, B, q.k, q.m);
+        if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(ACO_ERR_HIP, "event"); break; }
+        rc = launch_colony(S, L, &q, 0, P, default_tuning(q.k, L.nmax, q.m), best_tours,
+                           best_lens, ib, P, st);
+        if (rc != ACO_OK) break;
+        float ms = 0;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess ||
+            hipMemcpy(hib.data(), ib, (size_t)B * P * 8, hipMemcpyDeviceToHost) != hipSuccess) {
+            rc = fail(ACO_ERR_HIP, "timing a k candidate failed");
+            break;
+        }
+        per_iter_ms[c] = ms / P;
+        std::vector<int64_t> sofar(L0);
+        for (int i = 0; i < P; ++i) {
+            double acc = 0.0;
+            for (int b = 0; b < B; ++b) {
+                sofar[b] = std::min(sofar[b], hib[(size_t)b * P + i]);
+                acc += (double)sofar[b] / (double)L0[b];
+            }
+            quality[c][i] = acc / B;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    const hipError_t fe = hipFreeAsync(ib, st);
+    if (rc != ACO_OK) return rc;
+    if (fe != hipSuccess) return fail(ACO_ERR_HIP, "hipFreeAsync failed");
+    double target = 0.0;
+    for (size_t c = 0; c < ks.size(); ++c) target = std::max(target, quality[c][P - 1]);
+    double best_t = 1e300;
+    k_out = ks[0];
+    for (size_t c = 0; c < ks.size(); ++c) {
+        int i = 0;
+        while (i < P - 1 && quality[c][i] > target) ++i;
+        const double t = (i + 1) * per_iter_ms[c];
+        if (t < best_t) {
+            best_t = t;
+            k_out = ks[c];
+        }
+    }
+    return ACO_OK;
 }
 
 extern "C" int aco_run_batched(const int32_t *xy, const int64_t *offsets, int32_t B,
@@ -766,17 +973,28 @@ extern "C" int aco_run_batched(const int32_t *xy, const int64_t *offsets, int32_
                                void *stream, int32_t *tuned_out)
 {
     clear_error();
-    int rc = aco_batch_setup(xy, offsets, B, p, best_tours, best_lens, ws, ws_bytes, stream);
+    aco_params_t q;
+    int rc = load_params(p, q);
+    if (rc != ACO_OK) return rc;
+    if (q.k == 0) {   // k-auto: the workspace is sized for the largest candidate
+        aco_params_t big = q;
+        big.k = 1;
+        rc = validate_batch(offsets, B, &big);
+        if (rc != ACO_OK) return rc;
+        ACO_REQUIRE(xy && best_tours && best_lens && ws, "NULL array argument");
+        rc = choose_k(xy, offsets, B, &q, best_tours, best_lens, ws, ws_bytes, stream, q.k);
+        if (rc != ACO_OK) return rc;
+    }
+    rc = aco_batch_setup(xy, offsets, B, &q, best_tours, best_lens, ws, ws_bytes, stream);
     if (rc != ACO_OK) return rc;
     BatchLayoutHost L;
-    batch_layout(offsets, B, p->k, p->m, L);
+    batch_layout(offsets, B, q.k, q.m, L);
     hipStream_t st = as_stream(stream);
-    BatchState S = batch_state(ws, L, xy, B, p->k, p->m);
+    BatchState S = batch_state(ws, L, xy, B, q.k, q.m);
     int dev = 0;
     (void)hipGetDevice(&dev);
-    const auto key = std::make_tuple(dev, p->k, p->m, L.nmax, B);
-    Tuning best = default_tuning(p->k, L.nmax, p->m);
-    int32_t it = 0;
+    const auto key = std::make_tuple(dev, q.k, q.m, L.nmax, B);
+    Tuning best = default_tuning(q.k, L.nmax, q.m);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto f = g_tuned.find(key);
@@ -785,41 +1003,9 @@ extern "C" int aco_run_batched(const int32_t *xy, const int64_t *offsets, int32_
             autotune = 0;
         }
     }
-    if (autotune) {
-        // every candidate runs one real iteration (results do not depend on
-        // the configuration); the fastest runs the rest
-        const Tuning cand[] = {{4, ACO_VIS_BITS, 4},     {8, ACO_VIS_BITS, 4},
-                               {16, ACO_VIS_BITS, 4},    {4, ACO_VIS_BYTES, 4},
-                               {8, ACO_VIS_BYTES, 4},    {16, ACO_VIS_BYTES, 4},
-                               {4, ACO_VIS_BITS, 8},     {8, ACO_VIS_BITS, 8},
-                               {16, ACO_VIS_BITS, 8},    {8, ACO_VIS_BYTES, 8},
-                               {4, ACO_VIS_BITS_X4, 4},  {8, ACO_VIS_BITS_X4, 4},
-                               {16, ACO_VIS_BITS_X4, 4}, {4, ACO_VIS_BITS_X4, 8},
-                               {8, ACO_VIS_BITS_X4, 8},  {16, ACO_VIS_BITS_X4, 8}};
-        hipEvent_t e0, e1;
-        ACO_HIP_CHECK(hipEventCreate(&e0));
-        ACO_HIP_CHECK(hipEventCreate(&e1));
-        float best_ms = 1e30f;
-        for (const Tuning &c : cand) {
-            if (it >= p->iterations) break;
-            if (colony_lds(c.waves, c.layout, L.nmax, p->m) > max_lds_per_block()) continue;
-            if (c.layout == ACO_VIS_BITS_X4 && p->k > 16) continue;
-            ACO_HIP_CHECK(hipEventRecord(e0, st));
-            rc = launch_colony(S, L, p, it, 1, c, best_tours, best_lens,
-                               iter_best ? iter_best + it : nullptr, p->iterations, st);
-            if (rc != ACO_OK) return rc;
-            ACO_HIP_CHECK(hipEventRecord(e1, st));
-            ACO_HIP_CHECK(hipEventSynchronize(e1));
-            float ms = 0;
-            ACO_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = c;
-            }
-            ++it;
-        }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
+    if (autotune && q.iterations > 0) {
+        rc = tune_shape(S, L, &q, best_tours, best_lens, st, best);
+        if (rc != ACO_OK) return rc;
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tuned[key] = best;
     }
@@ -827,10 +1013,11 @@ extern "C" int aco_run_batched(const int32_t *xy, const int64_t *offsets, int32_
         tuned_out[0] = best.waves;
         tuned_out[1] = best.layout;
         tuned_out[2] = best.occ;
+        tuned_out[3] = q.k;
     }
-    if (it < p->iterations) {
-        rc = launch_colony(S, L, p, it, p->iterations - it, best, best_tours, best_lens,
-                           iter_best ? iter_best + it : nullptr, p->iterations, st);
+    if (q.iterations > 0) {
+        rc = launch_colony(S, L, &q, 0, q.iterations, best, best_tours, best_lens, iter_best,
+                           q.iterations, st);
         if (rc != ACO_OK) return rc;
     }
     return ACO_OK;

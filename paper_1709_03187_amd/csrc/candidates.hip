@@ -189,10 +189,11 @@ __global__ void k_eta(const int32_t *__restrict__ nnd, const float *__restrict__
 // The nearest-neighbour tour from city 0 by one wave on cell-order positions
 // (the visited bits are the workgroup's LDS).  nn and nnd are not needed: the
 // grid's 64-NN table by position starts with the candidate list.
-__global__ __launch_bounds__(kWave) void k_nn_tour(int32_t n, const void *grid, int32_t *tour)
+__global__ __launch_bounds__(kWave) void k_nn_tour(int32_t n, const void *grid, int32_t *tour,
+                                                  uint32_t *err)
 {
     extern __shared__ uint32_t vis[];
-    nn_tour_positions(grid_view(grid), n, VisBits{vis}, tour);
+    nn_tour_positions(grid_view(grid), n, VisBits{vis}, tour, err);
 }
 
 // Closed length of one tour by one workgroup of 256 threads (exact integer
@@ -341,13 +342,17 @@ extern "C" int aco_init_pheromone(const int32_t *xy, int32_t n, int32_t k, const
     if (lds > 65536)
         ACO_HIP_CHECK(hipFuncSetAttribute((const void *)k_nn_tour,
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    k_nn_tour<<<1, kWave, lds, st>>>(n, grid, nn_tour);
+    uint32_t *err = device_error_word();
+    if (!err) return ACO_ERR_HIP;
+    k_nn_tour<<<1, kWave, lds, st>>>(n, grid, nn_tour, err);
     ACO_LAUNCH_CHECK("k_nn_tour");
     k_closed_length<<<1, 256, 0, st>>>(xy, nn_tour, n, dlen);
     ACO_LAUNCH_CHECK("k_closed_length");
     int64_t L = 0;
     ACO_HIP_CHECK(hipMemcpyAsync(&L, dlen, 8, hipMemcpyDeviceToHost, st));
     ACO_HIP_CHECK(hipStreamSynchronize(st));
+    const int rc = report_device_error(st);
+    if (rc != ACO_OK) return rc;
     if (L <= 0)
         return fail(ACO_ERR_DEGENERATE, "nearest-neighbour tour has length %lld", (long long)L);
     const float t0 = (float)(1.0 / ((double)n * (double)L));

@@ -73,6 +73,13 @@ struct VisBits {
     {
         for (int i = lane; i < ((n + 31) >> 5); i += kWave) w[i] = ~0u;
     }
+    // this lane's share of the count of marked cities (after clear and set)
+    __device__ __forceinline__ int count(int n, int lane) const
+    {
+        int c = 0;
+        for (int i = lane; i < ((n + 31) >> 5); i += kWave) c += __popc(w[i]);
+        return c;
+    }
 };
 
 struct VisBytes {
@@ -91,6 +98,13 @@ struct VisBytes {
     {
         uint32_t *w = (uint32_t *)b;
         for (int i = lane; i < ((n + 3) >> 2); i += kWave) w[i] = 0x01010101u;
+    }
+    __device__ __forceinline__ int count(int n, int lane) const
+    {
+        const uint32_t *w = (const uint32_t *)b;
+        int c = 0;
+        for (int i = lane; i < ((n + 3) >> 2); i += kWave) c += __popc(w[i] & 0x01010101u);
+        return c;
     }
 };
 
@@ -186,6 +200,71 @@ struct AntTask {
     // Independent Roulette only: LDS for one block's uniforms, 64 steps x
     // ir_words_per_step(k) words (filled at the start of each block of steps)
     uint32_t *ir_words = nullptr;
+    uint32_t *err = nullptr;   // the device's error word (guards), or nullptr
+    uint64_t *prof = nullptr;  // step profile build only: kProfFields counters, or nullptr
+};
+
+// No closed tour is this long: every edge is shorter than 2^31 (coordinates
+// within +-(2^29 - 1)), so a length of n * 2^31 or more is not a tour's.
+__device__ __forceinline__ bool possible_tour_length(int64_t L, int32_t n)
+{
+    return L > 0 && L < ((int64_t)n << 31);
+}
+
+// Step profile (a separate build with ACO_STEP_PROFILE defined; the library
+// itself is built without it).  Each ant's wave stamps the shader clock
+// (s_memtime) at three points of every construction step: once the row of
+// the current city has arrived, once the next city is known, and at the end
+// of the step (and once per block of 64 steps); the stamps are read only at
+// later LDS waits, so they add no wait of their own.  Per ant (16 counters,
+// lane 0 writes them at the end):
+enum StepProfile {
+    kProfTotal = 0,      // clock ticks of the whole build_ant call
+    kProfRowWait = 1,    // end of the previous step (or block top) until the row of
+                         // the current city has arrived
+    kProfTail = 2,       // next city known until the end of the step (miss load
+                         // issue, visited bit, staging)
+    kProfBlock = 3,      // between blocks: Philox words, stores, tour entries
+    kProfDecide = 4,     // row arrived until next city known, by path (+0..2):
+                         // roulette scan, nearest-unvisited fallback,
+                         // Independent Roulette
+    kProfCount = 7,      // steps by the same paths (+0..2)
+    kProfSteps = 10,     // steps
+    kProfFields = 16
+};
+#ifdef ACO_STEP_PROFILE
+#define ACO_PROF(...) __VA_ARGS__
+#else
+#define ACO_PROF(...)
+#endif
+
+// The counters of one ant, held in scalar registers (no indexed array, which
+// would live in scratch memory).
+struct StepCounters {
+    uint64_t total = 0, row = 0, tail = 0, block = 0, steps = 0;
+    uint64_t dec[3] = {}, cnt[3] = {};
+    __device__ __forceinline__ void decided(int path, uint64_t dt)
+    {
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            dec[p] += path == p ? dt : 0;
+            cnt[p] += path == p ? 1 : 0;
+        }
+        ++steps;
+    }
+    __device__ __forceinline__ void store(uint64_t *out) const
+    {
+        out[kProfTotal] = total;
+        out[kProfRowWait] = row;
+        out[kProfTail] = tail;
+        out[kProfBlock] = block;
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            out[kProfDecide + p] = dec[p];
+            out[kProfCount + p] = cnt[p];
+        }
+        out[kProfSteps] = steps;
+    }
 };
 
 // Words of Independent Roulette uniforms held per step: k rounded up to the
@@ -214,6 +293,10 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
     const int lane = lane_id();
     const int32_t n = T.n, k = T.k;
     auto visited = [&](int city) { return vis.test(city); };
+    // (stamps of the previous step, added up once its results are known to
+    // have arrived: after the next LDS wait, so that no wait is added)
+    ACO_PROF(StepCounters pc; const uint64_t t_start = __builtin_amdgcn_s_memtime();
+             uint64_t t_last = t_start, q0 = 0, q1 = 0, q2 = 0, q3 = 0; int qpath = -1;)
 
     const GridView g = grid();              // read once: no state carried through the loop
     uint32_t rnd = colony_draw(T.seed, T.iteration, T.ant, (uint32_t)lane);
@@ -244,15 +327,18 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
         if (lane == 0) vis.set(start);
         c = start;
     } else {
-        // every city visited except the n - keep to rebuild; the kept part is
-        // copied to the tour (no construction record: slot kNoSlot)
-        // (a local best is a permutation; the range checks only keep a wrong
-        // one from turning into an out-of-bounds access)
-        vis.fill(n, lane);
-        for (int32_t j = lane; j < n - keep; j += kWave) {
-            const int32_t city = T.lbest[(s_pos + keep + j) % n];
-            if ((uint32_t)city < (uint32_t)n) vis.unset(space.from_city(g, city));
-        }
+        // the kept part is copied to the tour (no construction record: slot
+        // kNoSlot); meanwhile the local best is checked to be a permutation:
+        // its entries, marked by city index in the (cleared) bitmask, must
+        // set n distinct bits.  A wrong row trips a guard (out-of-range
+        // entries are read as city 0, so every access stays in range).
+        // With its length given, that length must be a possible one, else the
+        // kept part's length is summed edge by edge.
+        const bool use_len =
+            kLen && T.lbest_len && possible_tour_length(*T.lbest_len, n);
+        if (kLen && T.lbest_len && !use_len && lane == 0) flag_error(T.err, kErrLbestLen);
+        vis.clear(n, lane);
+        bool row_ok = true;
         // copy eight positions per lane per round, loads issued before stores
         constexpr int kU = 8;
         int2 kprev = make_int2(0, 0);   // coordinates of kept position t0 - 1
@@ -269,18 +355,19 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
             for (int u = 0; u < kU; ++u) {
                 const int32_t t = t0 + u * kWave + lane;
                 if (t < keep) {
+                    const bool in = (uint32_t)v[u] < (uint32_t)n;
+                    row_ok &= in;
+                    v[u] = in ? v[u] : 0;
                     T.tour[t] = v[u];
                     T.slots[t] = (uint8_t)kNoSlot;
                     if constexpr (kProb) T.prob[t] = 1.0f;
+                    vis.set(v[u]);
                 }
             }
-            if (kLen && !T.lbest_len) {
+            if (kLen && !use_len) {
                 int2 pc[kU];
 #pragma unroll
-                for (int u = 0; u < kU; ++u) {
-                    const int32_t c = (uint32_t)v[u] < (uint32_t)n ? v[u] : 0;
-                    pc[u] = ((const int2 *)T.xy)[c];
-                }
+                for (int u = 0; u < kU; ++u) pc[u] = ((const int2 *)T.xy)[v[u]];   // in range
 #pragma unroll
                 for (int u = 0; u < kU; ++u) {
                     const int32_t t = t0 + u * kWave + lane;
@@ -293,7 +380,25 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
                 }
             }
         }
-        if (kLen && T.lbest_len) {
+        // the rebuilt part's entries complete the permutation check; then the
+        // bitmask is set up for the construction (by the ant's city space):
+        // every city visited except the n - keep to rebuild
+        for (int32_t j = lane; j < n - keep; j += kWave) {
+            const int32_t city = T.lbest[(s_pos + keep + j) % n];
+            const bool in = (uint32_t)city < (uint32_t)n;
+            row_ok &= in;
+            vis.set(in ? city : 0);
+        }
+        int32_t marked = vis.count(n, lane);
+        for (int off = kWave / 2; off > 0; off >>= 1) marked += __shfl_xor(marked, off);
+        if (__builtin_amdgcn_ballot_w64(!row_ok) != 0ull || marked != n)
+            if (lane == 0) flag_error(T.err, kErrLbestCity);
+        vis.fill(n, lane);
+        for (int32_t j = lane; j < n - keep; j += kWave) {
+            const int32_t city = T.lbest[(s_pos + keep + j) % n];
+            if ((uint32_t)city < (uint32_t)n) vis.unset(space.from_city(g, city));
+        }
+        if (kLen && use_len) {
             // the kept part's internal edges: the local best's length minus its
             // n - keep + 1 edges from the last kept city round to the first
             if (lane == 0) part += *T.lbest_len;
@@ -353,7 +458,10 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
     // the guess
     CandW eg = T.rows[(int64_t)c * k + lr], en = eg;
     bool hit = true;
+    bool next_bad = false;   // a next city came out of range (wave-uniform)
     for (int32_t base = first & ~(kWave - 1); base < n; base += kWave) {
+        ACO_PROF(const uint64_t tb = __builtin_amdgcn_s_memtime(); pc.block += tb - t_last;
+                 t_last = tb;)
         if (base > 0) rnd = colony_draw(T.seed, T.iteration, T.ant, (uint32_t)(base + lane));
         if constexpr (kSampler != 0) {
             // Independent Roulette: the block's uniforms, off the steps' critical
@@ -375,8 +483,11 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
         const int32_t last = min(base + kWave - 1, n - 1);
         for (int32_t step = max(base, first); step <= last; ++step) {
             const int idx = step - base;
+            ACO_PROF(int path = 0;)
             const CandW e = hit ? eg : en;
             const int32_t j = e.city;
+            ACO_PROF(asm volatile("" ::"s"(__builtin_amdgcn_readfirstlane(j)));
+                     const uint64_t t1 = __builtin_amdgcn_s_memtime(); const uint64_t t0 = t_last;)
             const uint32_t seen = visited(j);          // every lane reads a valid word
             // Independent Roulette: this step's uniform for candidate lr (read
             // beside the visited word)
@@ -386,6 +497,11 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
             // lane mask re-materialised in a vector register)
             const uint64_t any = __builtin_amdgcn_ballot_w64(seen == 0u) &
                                  __builtin_amdgcn_ballot_w64(e.w > 0.0f) & act_mask;
+            ACO_PROF(if (qpath >= 0) {
+                pc.row += q1 - q0;
+                pc.decided(qpath, q2 - q1);
+                pc.tail += q3 - q2;
+            })
             // the first candidate that can be chosen is the likeliest next city
             // (rows are in distance order): its row is loaded while the scan runs
             // (issued without a branch: with no live candidate the row of lane
@@ -400,6 +516,7 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
             if constexpr (kSampler != 0) {
                 // Independent Roulette: the largest product wins
                 if (any) {
+                    ACO_PROF(path = 2;)
                     const double v = live ? wv * ((double)xw * 0x1p-32) : -1.0;
                     const double vmax = read_lane_f64(wave_incl_max_f64(v, KP), k - 1);
                     const uint64_t top = __builtin_amdgcn_ballot_w64(v == vmax) & any;
@@ -407,6 +524,7 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
                     jn = read_lane_i32(j, f);
                     slot = (uint32_t)f;
                 } else {
+                    ACO_PROF(path = 1;)
                     jn = space.fallback(g, T.xy, c, vis, visited);
                     slot = kNoSlot;
                 }
@@ -423,16 +541,21 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
                 // leaves none, the last slot that can be chosen
                 const int f = hit ? __ffsll((unsigned long long)hit) - 1
                                   : 63 - __clzll((long long)any);
+                if constexpr (kProb) prob = (float)(read_lane_f64(wv, f) / S);
                 jn = read_lane_i32(j, f);
                 slot = (uint32_t)f;
-                if constexpr (kProb) prob = (float)(read_lane_f64(wv, f) / S);
             } else {
+                ACO_PROF(path = 1;)
                 jn = space.fallback(g, T.xy, c, vis, visited);
                 slot = kNoSlot;
             }
-            // a city index is always in range here; the clamp only keeps a logic
-            // error from turning into an out-of-bounds access (tests see the tour)
-            jn = ((uint32_t)jn < (uint32_t)n) ? jn : start;
+            ACO_PROF(asm volatile("" ::"s"(jn)); const uint64_t t2 = __builtin_amdgcn_s_memtime();)
+            // a city index is always in range here; the guard keeps a logic
+            // error from turning into an out-of-bounds access (reported once
+            // the tour is done, so the step stays branch-free and scalar)
+            const bool out = (uint32_t)jn >= (uint32_t)n;
+            next_bad |= out;
+            jn = out ? start : jn;
             hit = jn == guess;
             if (!hit) en = T.rows[(int64_t)jn * k + lr];
             if (lane == 0) vis.set(jn);
@@ -442,6 +565,8 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
                 if constexpr (kProb) st_prob = prob;
             }
             c = jn;
+            ACO_PROF(const uint64_t t3 = __builtin_amdgcn_s_memtime(); t_last = t3; q0 = t0;
+                     q1 = t1; q2 = t2; q3 = t3; qpath = path;)
         }
         // records go out now; the tour entries need a load (city index and
         // coordinates by position), so they go out one block later, when that
@@ -469,10 +594,22 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
     }
     if (pend_any) ACO_FLUSH_PENDING();
 #undef ACO_FLUSH_PENDING
+    if (next_bad && lane == 0) flag_error(T.err, kErrNextCity);
+    ACO_PROF(if (qpath >= 0) {
+        pc.row += q1 - q0;
+        pc.decided(qpath, q2 - q1);
+        pc.tail += q3 - q2;
+    } if (T.prof && lane == 0) {
+        pc.total = __builtin_amdgcn_s_memtime() - t_start;
+        pc.store(T.prof);
+    })
     if constexpr (!kLen) return 0;
     // the closing edge (position n - 1 to position 0), then one reduction
     if (lane == 0) part += nint_sqrt(sq_dist(carry.x, carry.y, head.x, head.y));
     for (int off = kWave / 2; off > 0; off >>= 1) part += __shfl_xor(part, off);
+    // a local best length that does not match its row can leave the sum at a
+    // length no tour has
+    if (keep > 0 && !possible_tour_length(part, n) && lane == 0) flag_error(T.err, kErrLbestLen);
     return part;
 }
 
@@ -617,7 +754,8 @@ __device__ inline void knn_city_wide(const GridView &g, const int4 me, int kx, u
 template <class Vis>
 __device__ int64_t nn_tour_wave(const int32_t *__restrict__ xy, int32_t n, int32_t k,
                                 const int32_t *__restrict__ nn, const int32_t *__restrict__ nnd,
-                                const GridView &g, const Vis &vis, int32_t *tour)
+                                const GridView &g, const Vis &vis, int32_t *tour,
+                                uint32_t *err = nullptr)
 {
     const int lane = lane_id();
     vis.clear(n, lane);
@@ -626,6 +764,7 @@ __device__ int64_t nn_tour_wave(const int32_t *__restrict__ xy, int32_t n, int32
     int32_t c = 0;
     int64_t L = 0;
     int32_t stage = 0;   // lane t holds tour[base + t]
+    bool next_bad = false;
     for (int32_t t = 1; t < n; ++t) {
         const int64_t rb = (int64_t)c * k;
         int32_t j = 0, d = 0;
@@ -643,7 +782,9 @@ __device__ int64_t nn_tour_wave(const int32_t *__restrict__ xy, int32_t n, int32
             dn = read_lane_i32(d, f);
         } else {
             jn = fallback_city(g, xy, c, visited);
-            jn = ((uint32_t)jn < (uint32_t)n) ? jn : 0;   // range guard, as in build_ant
+            const bool out = (uint32_t)jn >= (uint32_t)n;   // range guard, as in build_ant
+            next_bad |= out;
+            jn = out ? 0 : jn;
             dn = nint_sqrt(sq_dist(xy[2 * (int64_t)c], xy[2 * (int64_t)c + 1],
                                    xy[2 * (int64_t)jn], xy[2 * (int64_t)jn + 1]));
         }
@@ -657,6 +798,7 @@ __device__ int64_t nn_tour_wave(const int32_t *__restrict__ xy, int32_t n, int32
         c = jn;
     }
     L += nint_sqrt(sq_dist(xy[2 * (int64_t)c], xy[2 * (int64_t)c + 1], xy[0], xy[1]));
+    if (next_bad && lane == 0) flag_error(err, kErrNextCity);
     return L;
 }
 
@@ -667,7 +809,7 @@ __device__ int64_t nn_tour_wave(const int32_t *__restrict__ xy, int32_t n, int32
 // unvisited city.  Writes the tour as city indices; its length is summed
 // afterwards, off this sequential loop.
 __device__ inline void nn_tour_positions(const GridView &g, int32_t n, const VisBits &vis,
-                                         int32_t *tour)
+                                         int32_t *tour, uint32_t *err = nullptr)
 {
     const int lane = lane_id();
     vis.clear(n, lane);
@@ -676,6 +818,7 @@ __device__ inline void nn_tour_positions(const GridView &g, int32_t n, const Vis
     int32_t c = g.pinv[0];
     if (lane == 0) vis.set(c);
     int32_t stage = c;   // lane t holds the position of tour[base + t]
+    bool next_bad = false;
     for (int32_t t = 1; t < n; ++t) {
         int32_t j = 0;
         bool unv = false;
@@ -686,7 +829,9 @@ __device__ inline void nn_tour_positions(const GridView &g, int32_t n, const Vis
         const uint64_t bal = __ballot(unv);
         int32_t jn = bal ? read_lane_i32(j, __ffsll((unsigned long long)bal) - 1)
                          : fallback_position(g, c, vp);
-        jn = ((uint32_t)jn < (uint32_t)n) ? jn : c;   // range guard, as in build_ant
+        const bool out = (uint32_t)jn >= (uint32_t)n;   // range guard, as in build_ant
+        next_bad |= out;
+        jn = out ? c : jn;
         if (lane == 0) vis.set(jn);
         if (lane == (t & 63)) stage = jn;
         if ((t & 63) == 63 || t == n - 1) {
@@ -695,6 +840,7 @@ __device__ inline void nn_tour_positions(const GridView &g, int32_t n, const Vis
         }
         c = jn;
     }
+    if (next_bad && lane == 0) flag_error(err, kErrNextCity);
 }
 
 }  // namespace aco

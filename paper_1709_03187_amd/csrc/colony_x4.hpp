@@ -27,6 +27,7 @@ struct Ants4Task {
     uint64_t seed;
     int32_t *tours;        // [m][n]
     uint8_t *slots;        // [m][n]
+    uint32_t *err;         // the device's error word, or nullptr
 };
 
 // LDS of one such wave: four visited bitmasks of set_bytes each (a multiple of
@@ -86,6 +87,7 @@ __device__ void build_ants4(const Ants4Task &T, unsigned char *lds, size_t set_b
 
     CandW eg = T.rows[(int64_t)c * k + lr], en = eg;
     bool hit = true;
+    bool next_bad = false;
     for (int32_t base = 0; base < n; base += kWave) {
         if (base > 0) fill_draws(base);
         const int32_t last = min(base + kWave - 1, n - 1);
@@ -132,8 +134,11 @@ __device__ void build_ants4(const Ants4Task &T, unsigned char *lds, size_t set_b
                                                  [&](int city) { return vp.test(city); });
                 jn = q == p ? jp : jn;
             }
-            // always in range; the clamp only keeps a logic error in bounds
-            jn = ((uint32_t)jn < (uint32_t)n) ? jn : start;
+            // always in range; the guard keeps a logic error in bounds (reported
+            // once the tours are done)
+            const bool out = (uint32_t)jn >= (uint32_t)n;
+            next_bad |= __builtin_amdgcn_ballot_w64(out && mine) != 0ull;
+            jn = out ? start : jn;
             hit = jn == guess;
             if (!hit) en = T.rows[(int64_t)jn * k + lr];
             if (gr == 0 && mine) {
@@ -152,6 +157,7 @@ __device__ void build_ants4(const Ants4Task &T, unsigned char *lds, size_t set_b
             }
         }
     }
+    if (next_bad && lane == 0) flag_error(T.err, kErrNextCity);
 }
 
 }  // namespace aco

@@ -23,6 +23,23 @@ int num_cus();
 
 inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
+// The device error word: guard bits (DeviceError, in device.hpp) that
+// kernels set when device data breaks a stated precondition.
+
+// Device address of the current device's error word (a `__device__` array of
+// the library, located once per device; no allocation), or nullptr after a
+// HIP error (message recorded).
+uint32_t *device_error_word();
+// Takes the error word (atomically reset to 0) in stream order, synchronises
+// with `st` and returns ACO_ERR_DEVICE with a message naming the tripped
+// guards, or ACO_OK.
+int report_device_error(hipStream_t st);
+
+// Copies the caller's parameters into `out`: only its struct_size bytes are
+// read, later fields take their defaults.  INVALID_ARG when p is NULL or its
+// struct_size does not cover the fields through seed.
+int load_params(const aco_params_t *p, aco_params_t &out);
+
 // Bytes of the per-ant visited bitmask (one bit per city).
 inline size_t bitmask_bytes(int64_t n) { return (size_t)((n + 31) / 32) * 4; }
 

@@ -9,29 +9,34 @@
 // sum exceeds u * S with a ballot.  When no unvisited candidate has positive
 // weight the wave takes the nearest unvisited city (256-NN table, then grid).
 // The tour's length is summed exactly inside the same kernel.
+#include <algorithm>
 #include <cmath>
+#include <cstddef>
+#include <cstring>
 
 #include "colony.hpp"
 #include "common.hpp"
 
 namespace aco {
 
-// Choice weights of every row (thread per position in cell order): row q is
-// the row of city pts[q], and its candidates are named by position.
+// Choice weights of every row, by position in cell order: the row of city i
+// is row pinv[i] of the table, its candidates named by position.  One thread
+// per city in index order, so nn, tau and eta_b are read as streams; each
+// thread writes its whole row (one 128-byte line at k = 16).
 struct ToPosition {
     const int32_t *pinv;
     __device__ __forceinline__ int32_t operator()(int32_t c) const { return pinv[c]; }
 };
 
-__global__ void k_choice_info(const int4 *__restrict__ pts, const int32_t *__restrict__ pinv,
-                              const int32_t *__restrict__ nn, const float *__restrict__ tau,
-                              const float *__restrict__ eta_b, int32_t n, int32_t k, double alpha,
-                              CandW *__restrict__ rows)
+__global__ void k_choice_info(const int32_t *__restrict__ pinv, const int32_t *__restrict__ nn,
+                              const float *__restrict__ tau, const float *__restrict__ eta_b,
+                              int32_t n, int32_t k, double alpha, CandW *__restrict__ rows)
 {
-    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (q >= n) return;
-    const int64_t rb = (int64_t)pts[q].z * k;
-    choice_row(nn + rb, tau + rb, eta_b + rb, k, alpha, rows + q * k, ToPosition{pinv});
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t rb = i * k;
+    choice_row(nn + rb, tau + rb, eta_b + rb, k, alpha, rows + (int64_t)pinv[i] * k,
+               ToPosition{pinv});
 }
 
 struct ConstructArgs {
@@ -52,6 +57,8 @@ struct ConstructArgs {
     int32_t max_modify;
     int32_t m;              // ants in this launch
     int32_t ant_lds;        // LDS bytes per ant (visited set, Independent Roulette's uniforms)
+    uint32_t *err;          // the device's error word
+    uint64_t *prof;         // step profile build: [m][kProfFields] counters, else nullptr
 };
 
 // One ant per wave, up to four waves (ants) per workgroup, each with its own
@@ -86,6 +93,8 @@ __global__ __launch_bounds__(4 * kWave) void k_construct(ConstructArgs A)
     T.lbest_len = A.lbest && A.lbest_len ? A.lbest_len + a : nullptr;
     T.p_threshold = A.p_threshold;
     T.max_modify = A.max_modify;
+    T.err = A.err;
+    T.prof = A.prof ? A.prof + (int64_t)a * kProfFields : nullptr;
     if constexpr (kSampler != 0)   // the uniforms follow the visited set, 16-byte aligned
         T.ir_words = vis + ((((int64_t)A.n + 31) / 32 * 4 + 15) & ~(int64_t)15) / 4;
     const int64_t len = build_ant_fixed<KP, kProb, PositionSpace, kSampler, true>(
@@ -96,6 +105,16 @@ __global__ __launch_bounds__(4 * kWave) void k_construct(ConstructArgs A)
 }  // namespace aco
 
 using namespace aco;
+
+// Where the step profile build writes its counters (set by
+// aco_step_profile_buffer; always null in the library itself).
+static uint64_t *g_step_profile = nullptr;
+
+#ifdef ACO_STEP_PROFILE
+// Step profile build only: the device buffer ([m][16] uint64) that the next
+// constructions fill with each ant's clock counters (NULL to stop).
+extern "C" void aco_step_profile_buffer(uint64_t *buf) { g_step_profile = buf; }
+#endif
 
 extern "C" size_t aco_construct_workspace_bytes(int32_t n, int32_t k)
 {
@@ -130,10 +149,8 @@ static int construct(const int32_t *xy, int32_t n, int32_t k, const int32_t *nn,
     hipStream_t st = as_stream(stream);
     CandW *rows = (CandW *)ws;
     const GridLayout lay(n);
-    const int4 *pts = (const int4 *)((const char *)grid + lay.pts);
     const int32_t *pinv = (const int32_t *)((const char *)grid + lay.pinv);
-    k_choice_info<<<blocks_for(n, 256), 256, 0, st>>>(pts, pinv, nn, tau, eta_b, n, k, alpha,
-                                                        rows);
+    k_choice_info<<<blocks_for(n, 256), 256, 0, st>>>(pinv, nn, tau, eta_b, n, k, alpha, rows);
     ACO_LAUNCH_CHECK("k_choice_info");
     void (*kern)(ConstructArgs);
     if (sampler == ACO_SAMPLER_INDEPENDENT)   // no step probabilities (checked above)
@@ -158,9 +175,12 @@ static int construct(const int32_t *xy, int32_t n, int32_t k, const int32_t *nn,
         ACO_HIP_CHECK(hipFuncSetAttribute((const void *)kern,
                                           hipFuncAttributeMaxDynamicSharedMemorySize,
                                           (int)lds_req));
+    uint32_t *err = device_error_word();
+    if (!err) return ACO_ERR_HIP;
     ConstructArgs A{xy,    rows,    grid,      n,     k,           ant0,
                     (uint32_t)iteration,       seed,      tours, lengths, slots,
-                    step_prob, lbest,   lbest_len, p_threshold, max_modify, m, (int32_t)lds};
+                    step_prob, lbest,   lbest_len, p_threshold, max_modify, m, (int32_t)lds,
+                    err, g_step_profile};
     kern<<<blocks, wpb * kWave, lds_req, st>>>(A);
     ACO_LAUNCH_CHECK("k_construct");
     return ACO_OK;
@@ -207,8 +227,14 @@ extern "C" int aco_construct_ex(const int32_t *xy, int32_t n, int32_t k, const i
                                 float *step_prob, void *ws, size_t ws_bytes, void *stream)
 {
     clear_error();
-    aco_construct_opts_t o{ACO_SAMPLER_ROULETTE, 0.0, 0, nullptr, nullptr};
-    if (opts) o = *opts;
+    aco_construct_opts_t o{sizeof(aco_construct_opts_t), ACO_SAMPLER_ROULETTE, 0.0, 0, nullptr,
+                           nullptr};
+    if (opts) {
+        const size_t least = offsetof(aco_construct_opts_t, lbest) + sizeof(o.lbest);
+        ACO_REQUIRE(opts->struct_size >= least, "opts->struct_size = %u is below %zu",
+                    opts->struct_size, least);
+        std::memcpy(&o, opts, std::min((size_t)opts->struct_size, sizeof(o)));
+    }
     ACO_REQUIRE(o.sampler == ACO_SAMPLER_ROULETTE || o.sampler == ACO_SAMPLER_INDEPENDENT,
                 "sampler = %d unknown", o.sampler);
     ACO_REQUIRE(o.sampler == ACO_SAMPLER_ROULETTE || !step_prob,

@@ -75,6 +75,27 @@ __device__ __forceinline__ int32_t nint_sqrt(int64_t s64)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
+// Guards a kernel can trip on device data that the host cannot check before
+// the launch.  A kernel that trips one keeps every access in range, finishes
+// normally and ORs the bit into the device's error word; the next entry point
+// that synchronises (or aco_device_error) reports it as ACO_ERR_DEVICE.
+enum DeviceError : uint32_t {
+    kErrNextCity = 1u,    // construction or NN tour: a next city out of range (internal)
+    kErrLbestCity = 2u,   // a local best row is not a permutation of 0..n-1
+    kErrLbestLen = 4u,    // a local best length that no tour can have, or a kept part's
+                          // length that came out negative
+    kErrTourCity = 8u,    // pheromone update: a tour holds a city out of range
+    kErrLength = 16u,     // pheromone update: a length <= 0, or a deposit sum that could
+                          // overflow int64 (m * quantum >= 2^63)
+};
+
+// Records a tripped guard in the device's error word (bits of DeviceError);
+// err may be nullptr (no report).  Callers let one lane call it.
+__device__ __forceinline__ void flag_error(uint32_t *err, uint32_t bit)
+{
+    if (err) atomicOr(err, bit);
+}
+
 __device__ __forceinline__ int32_t read_lane_i32(int32_t v, int lane)
 {
     return __builtin_amdgcn_readlane(v, lane);

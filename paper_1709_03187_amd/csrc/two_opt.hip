@@ -600,5 +600,5 @@ extern "C" int aco_two_opt(const int32_t *xy, int32_t n, int32_t m, int32_t *tou
         ACO_HIP_CHECK(hipStreamSynchronize(st));
     }
     if (stats) *stats = out;
-    return ACO_OK;
+    return report_device_error(st);
 }

@@ -5,19 +5,25 @@
 // sum is independent of the order in which ants and edges arrive; the merge
 // then applies evaporation and the deposit with exactly two FP32 roundings.
 #include <cmath>
+#include <mutex>
 
 #include "common.hpp"
 #include "device.hpp"
 
 namespace aco {
 
+// q_a = floor(2^shift / L_a).  Every slot's sum stays below m * max q_a, so
+// m * q_a < 2^63 for every ant keeps the int64 sums exact; otherwise (or for
+// a length <= 0, whose quantum is set to 0) a guard trips.
 __global__ void k_quanta(const int64_t *__restrict__ lengths, int32_t m, int32_t shift,
-                         int64_t *__restrict__ q)
+                         int64_t *__restrict__ q, uint32_t *err)
 {
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= m) return;
     const int64_t L = lengths[a];
-    q[a] = L > 0 ? ((int64_t)1 << shift) / L : 0;
+    const int64_t qa = L > 0 ? ((int64_t)1 << shift) / L : 0;
+    if (L <= 0 || qa > INT64_MAX / m) flag_error(err, kErrLength);
+    q[a] = qa;
 }
 
 __global__ void k_zero_i64(int64_t *p, int64_t count)
@@ -43,7 +49,7 @@ __device__ __forceinline__ int find_slot(const int32_t *__restrict__ nn, int64_t
 __global__ void k_deposit(const int32_t *__restrict__ nn, const int8_t *__restrict__ rev,
                           int32_t n, int32_t k, int32_t a0, const int32_t *__restrict__ tours,
                           const uint8_t *__restrict__ slots, const int64_t *__restrict__ q,
-                          unsigned long long *__restrict__ acc)
+                          unsigned long long *__restrict__ acc, uint32_t *err)
 {
     const int32_t a = a0 + (int32_t)blockIdx.y;
     const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -51,25 +57,29 @@ __global__ void k_deposit(const int32_t *__restrict__ nn, const int8_t *__restri
     const int64_t base = (int64_t)a * n;
     const int32_t i = tours[base + t];
     const int32_t j = tours[base + (t + 1 == n ? 0 : t + 1)];
-    if (i < 0 || i >= n || j < 0 || j >= n) return;
+    // not a tour of 0..n-1: nothing deposited for the edge, reported once per wave
+    const bool bad = i < 0 || i >= n || j < 0 || j >= n;
+    if (__builtin_amdgcn_ballot_w64(bad) != 0ull && lane_id() == 0) flag_error(err, kErrTourCity);
+    if (bad) return;
     const unsigned long long qa = (unsigned long long)q[a];
     const int64_t ri = (int64_t)i * k, rj = (int64_t)j * k;
     // A fallback move (slot 255) can still end on a candidate city: that happens
     // when every unvisited candidate has zero weight.  Such edges are located
     // by scanning the row, as are edges without a construction record.
     int r = -1;
-    if (slots && t + 1 < n) {
+    if (slots && t + 1 < n) {   // the record is trusted (checking it costs a gather)
         const uint32_t s = slots[base + t + 1];
         if (s < (uint32_t)k) r = (int)s;
     }
     if (r < 0) r = find_slot(nn, ri, k, j);
     const int r2 = (r >= 0) ? (int)rev[ri + r] : find_slot(nn, rj, k, i);
     // one atomic per undirected edge, into its canonical slot: the slot in the
-    // row of the smaller city when both directions are stored
-    if (r >= 0 && (r2 < 0 || i < j))
-        atomicAdd(&acc[ri + r], qa);
-    else if (r2 >= 0 && r2 < k)
-        atomicAdd(&acc[rj + r2], qa);
+    // row of the smaller city when both directions are stored (one atomic
+    // instruction for both cases)
+    const int64_t dst = (r >= 0 && (r2 < 0 || i < j)) ? ri + r
+                        : (r2 >= 0 && r2 < k)          ? rj + r2
+                                                        : -1;
+    if (dst >= 0) atomicAdd(&acc[dst], qa);
 }
 
 // tau = fl32(fl32(tau * f) + fl32(fl32(acc) * 2^-shift)); both products are
@@ -158,16 +168,21 @@ __global__ __launch_bounds__(256) void k_best_finish(const int64_t *__restrict__
 // Pheromone from the local best tours (the P-ACO variant of Section 3): the
 // quantum of local best a is q_a = floor(2^shift * L_g / L_a) with the ratio
 // in FP64 and L_g the shortest local best (one workgroup).
+// A length <= 0 trips a guard and gets quantum 0.
 __global__ __launch_bounds__(1024) void k_quanta_ratio(const int64_t *__restrict__ lbest_len,
                                                        int32_t m, int32_t shift,
-                                                       int64_t *__restrict__ q)
+                                                       int64_t *__restrict__ q, uint32_t *err)
 {
     __shared__ int64_t red[1024 / kWave];
     int64_t lmin = INT64_MAX;
-    for (int a = threadIdx.x; a < m; a += blockDim.x) lmin = lbest_len[a] < lmin ? lbest_len[a] : lmin;
-    const int64_t Lg = block_min_i64(lmin, red);
     for (int a = threadIdx.x; a < m; a += blockDim.x)
-        q[a] = (int64_t)floor(ldexp((double)Lg / (double)lbest_len[a], shift));
+        if (lbest_len[a] > 0) lmin = lbest_len[a] < lmin ? lbest_len[a] : lmin;
+    const int64_t Lg = block_min_i64(lmin, red);
+    for (int a = threadIdx.x; a < m; a += blockDim.x) {
+        const int64_t L = lbest_len[a];
+        if (L <= 0) flag_error(err, kErrLength);
+        q[a] = L > 0 ? (int64_t)floor(ldexp((double)Lg / (double)L, shift)) : 0;
+    }
 }
 
 // tau = fl32(base + fl32(fl32(acc) * scale)), no evaporation; the canonical
@@ -215,31 +230,36 @@ extern "C" size_t aco_update_workspace_bytes(int32_t n, int32_t k, int32_t m)
     return (size_t)n * (size_t)k * 8 + (((size_t)m * 8 + 255) & ~(size_t)255);
 }
 
-extern "C" int aco_update_pheromone(int32_t n, int32_t k, const int32_t *nn, const int8_t *rev,
-                                    int32_t m, const int32_t *tours, const uint8_t *slots,
-                                    const int64_t *lengths, double rho, int32_t deposit_shift,
-                                    float *tau, void *ws, size_t ws_bytes, void *stream)
+static int validate_update(int32_t n, int32_t k, const int32_t *nn, const int8_t *rev, int32_t m,
+                           const int32_t *tours, const int64_t *lengths, double rho,
+                           int32_t deposit_shift, const float *tau)
 {
-    clear_error();
     ACO_REQUIRE(n >= 3 && n <= (1 << 27), "n = %d out of range [3, 2^27]", n);
     ACO_REQUIRE(k >= 1 && k <= ACO_MAX_K && k <= n - 1, "k = %d out of range", k);
     ACO_REQUIRE(m >= 1 && m <= (1 << 20), "m = %d out of range [1, 2^20]", m);
     ACO_REQUIRE(rho > 0.0 && rho <= 1.0, "rho must lie in (0, 1]");
     ACO_REQUIRE(deposit_shift >= 0 && deposit_shift <= 62, "deposit_shift out of [0, 62]");
-    ACO_REQUIRE(nn && rev && tours && lengths && tau && ws, "NULL array argument");
-    const size_t need = aco_update_workspace_bytes(n, k, m);
-    if (ws_bytes < need)
-        return fail(ACO_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
-    hipStream_t st = as_stream(stream);
+    ACO_REQUIRE(nn && rev && tours && lengths && tau, "NULL array argument");
+    return ACO_OK;
+}
+
+// Evaporation and deposit with the slot sums and quanta in `ws` (validated).
+static int update_pheromone(int32_t n, int32_t k, const int32_t *nn, const int8_t *rev, int32_t m,
+                            const int32_t *tours, const uint8_t *slots, const int64_t *lengths,
+                            double rho, int32_t deposit_shift, float *tau, void *ws,
+                            hipStream_t st)
+{
     const int64_t nk = (int64_t)n * k;
     int64_t *acc = (int64_t *)ws;
     int64_t *q = (int64_t *)((char *)ws + (size_t)nk * 8);
+    uint32_t *err = device_error_word();
+    if (!err) return ACO_ERR_HIP;
     k_zero_i64<<<std::min(4096u, blocks_for(nk, 256)), 256, 0, st>>>(acc, nk);
-    k_quanta<<<blocks_for(m, 256), 256, 0, st>>>(lengths, m, deposit_shift, q);
+    k_quanta<<<blocks_for(m, 256), 256, 0, st>>>(lengths, m, deposit_shift, q, err);
     for (int32_t a0 = 0; a0 < m; a0 += 65535) {   // grid y is at most 65,535 ants
         const int32_t ma = m - a0 < 65535 ? m - a0 : 65535;
         k_deposit<<<dim3(blocks_for(n, 256), (unsigned)ma), 256, 0, st>>>(
-            nn, rev, n, k, a0, tours, slots, q, (unsigned long long *)acc);
+            nn, rev, n, k, a0, tours, slots, q, (unsigned long long *)acc, err);
     }
     const float f = (float)(1.0 - rho);
     const float scale = std::ldexp(1.0f, -deposit_shift);
@@ -247,6 +267,22 @@ extern "C" int aco_update_pheromone(int32_t n, int32_t k, const int32_t *nn, con
                                                                   scale);
     ACO_LAUNCH_CHECK("update kernels");
     return ACO_OK;
+}
+
+extern "C" int aco_update_pheromone(int32_t n, int32_t k, const int32_t *nn, const int8_t *rev,
+                                    int32_t m, const int32_t *tours, const uint8_t *slots,
+                                    const int64_t *lengths, double rho, int32_t deposit_shift,
+                                    float *tau, void *ws, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    int rc = validate_update(n, k, nn, rev, m, tours, lengths, rho, deposit_shift, tau);
+    if (rc != ACO_OK) return rc;
+    ACO_REQUIRE(ws, "NULL workspace");
+    const size_t need = aco_update_workspace_bytes(n, k, m);
+    if (ws_bytes < need)
+        return fail(ACO_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    return update_pheromone(n, k, nn, rev, m, tours, slots, lengths, rho, deposit_shift, tau, ws,
+                            as_stream(stream));
 }
 
 extern "C" int aco_track_best(int32_t n, int32_t m, const int32_t *tours, const int64_t *lengths,
@@ -296,6 +332,9 @@ extern "C" int aco_pheromone_local_best(int32_t n, int32_t k, const int32_t *nn,
     ACO_REQUIRE(m >= 1, "m = %d must be >= 1", m);
     ACO_REQUIRE(deposit_shift >= 0 && deposit_shift <= 62, "deposit_shift = %d out of [0, 62]",
                 deposit_shift);
+    // every quantum is at most 2^shift and a slot sums at most m of them
+    ACO_REQUIRE((int64_t)m <= (INT64_MAX >> deposit_shift),
+                "m * 2^deposit_shift = %d * 2^%d could overflow the int64 sums", m, deposit_shift);
     ACO_REQUIRE(std::isfinite(tau_base) && tau_base >= 0.0 && std::isfinite(delta) && delta >= 0.0,
                 "tau_base and delta must be finite and >= 0");
     ACO_REQUIRE(nn && rev && lbest && lbest_len && tau && ws, "NULL array argument");
@@ -306,12 +345,14 @@ extern "C" int aco_pheromone_local_best(int32_t n, int32_t k, const int32_t *nn,
     const int64_t nk = (int64_t)n * k;
     int64_t *acc = (int64_t *)ws;
     int64_t *q = (int64_t *)((char *)ws + (size_t)nk * 8);
+    uint32_t *err = device_error_word();
+    if (!err) return ACO_ERR_HIP;
     k_zero_i64<<<std::min(4096u, blocks_for(nk, 256)), 256, 0, st>>>(acc, nk);
-    k_quanta_ratio<<<1, 1024, 0, st>>>(lbest_len, m, deposit_shift, q);
+    k_quanta_ratio<<<1, 1024, 0, st>>>(lbest_len, m, deposit_shift, q, err);
     for (int32_t a0 = 0; a0 < m; a0 += 65535) {
         const int32_t ma = m - a0 < 65535 ? m - a0 : 65535;
         k_deposit<<<dim3(blocks_for(n, 256), (unsigned)ma), 256, 0, st>>>(
-            nn, rev, n, k, a0, lbest, nullptr, q, (unsigned long long *)acc);
+            nn, rev, n, k, a0, lbest, nullptr, q, (unsigned long long *)acc, err);
     }
     const float base = (float)tau_base;
     const float scale = (float)(delta * std::ldexp(1.0, -deposit_shift));

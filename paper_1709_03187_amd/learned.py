@@ -20,7 +20,7 @@ import numpy as np
 
 from . import (ACO_MLP_PARAMS, Batch, aco_edge_features, aco_features_workspace_bytes,
                aco_mlp_adam, aco_mlp_backward, aco_mlp_backward_workspace_bytes,
-               aco_tour_edge_labels)
+               aco_tour_edge_labels, aco_two_opt, aco_two_opt_workspace_bytes)
 
 
 @dataclass
@@ -31,16 +31,27 @@ class TrainingSet:
     seconds: float          # wall clock of colonies + features + labels
 
 
-def training_set(xys, k=16, m=64, iterations=30, seed=1, stream=None) -> TrainingSet:
+def training_set(xys, k=16, m=64, iterations=30, seed=1, stream=None, beta=2.0,
+                 two_opt_window=0) -> TrainingSet:
     """Run the batched colonies on the instances `xys` (list of int32 [n, 2])
-    and label every candidate edge by the best tour found."""
+    and label every candidate edge by the best tour found; with
+    two_opt_window > 0 each best tour is first made 2-optimal within that
+    window (windowed 2-opt to convergence), so the labels come from better
+    tours than the colony's own."""
     import torch
     t0 = time.perf_counter()
     sizes = np.array([len(x) for x in xys], np.int64)
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
-    bt = Batch(np.concatenate(xys), off, k=k, m=m, seed=seed, iterations=iterations)
+    bt = Batch(np.concatenate(xys), off, k=k, m=m, beta=beta, seed=seed, iterations=iterations)
     bt.run(autotune=0, stream=stream)
     N = bt.N
+    if two_opt_window:
+        tws = torch.empty(aco_two_opt_workspace_bytes(int(sizes.max()), 1, 1), dtype=torch.uint8,
+                          device="cuda")
+        for b in range(bt.B):
+            lo, hi = int(off[b]), int(off[b + 1])
+            aco_two_opt(bt.xy[lo:hi], hi - lo, 1, bt.best_tours[lo:hi], bt.best_lens[b:b + 1],
+                        None, two_opt_window, 1.0, seed, 0, 0, 1, tws, stream)
     nn = bt.view("nn", torch.int32, N * k)
     nnd = bt.view("nnd", torch.int32, N * k)
     rev = bt.view("rev", torch.int8, N * k)

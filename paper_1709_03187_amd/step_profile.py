@@ -1,0 +1,123 @@
+"""Where a construction step's time goes, from the step profile build.
+
+    python -m paper_1709_03187_amd.build --step-profile
+    python -m paper_1709_03187_amd.step_profile [--iterations 6] [--out FILE]
+
+Runs the n = 200,000 clustered workload (m = 1,024, k = 16) on
+libaco_step_profile.so, whose construction kernels stamp the shader clock at
+three points of every step (top of the step; the current row has arrived;
+the next city is known) and keep per-ant sums.  The last iteration's counters
+are summarised per ant-step: row wait, the decision by path (roulette scan,
+nearest-unvisited fallback), the rest of the step, and the work between
+blocks of 64 steps.  The tours are those of the
+library (the stamps change no result); the clock adds a few instructions per
+step, so the profiled kernel runs somewhat slower than the library's.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+PROFILE_LIB = os.path.join(HERE, "libaco_step_profile.so")
+FIELDS = ["total", "row_wait", "tail", "block", "decide_roulette", "decide_fallback",
+          "decide_ir", "count_roulette", "count_fallback", "count_ir", "steps"]
+NFIELDS = 16
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--iterations", type=int, default=6)
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args()
+    if not os.path.exists(PROFILE_LIB):
+        sys.exit(f"{PROFILE_LIB} is not built: python -m paper_1709_03187_amd.build --step-profile")
+    sys.path.insert(0, os.path.dirname(HERE))
+    import torch
+
+    import paper_1709_03187_amd as aco
+    from paper_1709_03187_amd import instances
+
+    aco.LIB_PATH = PROFILE_LIB      # the profile build in place of libaco.so
+    L = aco.lib()
+    L.aco_step_profile_buffer.restype = None
+    L.aco_step_profile_buffer.argtypes = [C.c_void_p]
+    cfg = instances.CONFIGS["c3"]
+    xy = instances.make_coords("c3")
+    n, m, k = cfg["n"], cfg["m"], cfg["k"]
+    col = aco.Colony(xy=xy, k=k, m=m, alpha=cfg["alpha"], beta=cfg["beta"], rho=cfg["rho"],
+                     seed=cfg["seed"])
+    col.setup()
+    prof = torch.zeros((m, NFIELDS), dtype=torch.int64, device="cuda")
+    last = args.iterations - 1
+    for it in range(args.iterations):
+        if it == last:
+            L.aco_step_profile_buffer(C.c_void_p(prof.data_ptr()))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        col.construct(it)
+        e1.record()
+        col.update()
+        torch.cuda.synchronize()
+        print(f"[step profile] iteration {it}: construct {e0.elapsed_time(e1):.2f} ms",
+              file=sys.stderr, flush=True)
+        if it == last:
+            construct_ms = e0.elapsed_time(e1)
+    L.aco_step_profile_buffer(None)
+    P = prof.cpu().numpy().astype(np.float64)
+    steps = P[:, FIELDS.index("steps")]
+    total = P[:, 0]
+    ticks_per_ms = total.max() / construct_ms
+    per_step = {f: float((P[:, i] / steps).mean()) for i, f in enumerate(FIELDS[:7])}
+    counts = {f[6:]: float(P[:, FIELDS.index(f)].sum() / steps.sum())
+              for f in FIELDS if f.startswith("count_")}
+    t_step = per_step["total"]
+    rows = [("row wait (end of the previous step until the current row has arrived)",
+             per_step["row_wait"]),
+            ("decision: visited test, guess load issue, FP64 scan, pick",
+             per_step["decide_roulette"]),
+            ("decision: nearest-unvisited fallback (visited test, table, grid)",
+             per_step["decide_fallback"]),
+            ("decision: Independent Roulette", per_step["decide_ir"]),
+            ("rest of the step (miss load issue, visited bit, staging)", per_step["tail"]),
+            ("between blocks of 64 steps (Philox, stores, tour entries)", per_step["block"])]
+    accounted = sum(v for _, v in rows)
+    lines = [f"# Construction step profile: n={n:,} clustered, m={m:,}, k={k}, iteration {last}",
+             "",
+             "Commands (repository root, one MI355X):",
+             "",
+             "    python -m paper_1709_03187_amd.build --step-profile",
+             "    python -m paper_1709_03187_amd.step_profile --iterations "
+             f"{args.iterations}" + (f" --out {args.out}" if args.out else ""),
+             "",
+             f"Profiled construction {construct_ms:.2f} ms; clock ticks of the slowest ant "
+             f"{total.max():.4g} ({ticks_per_ms:.4g} ticks per ms); mean "
+             f"{t_step:.1f} ticks per ant-step, {1e6 * t_step / ticks_per_ms:.1f} ns.",
+             "",
+             "| part of a step | ticks per ant-step (mean over ants) | share |",
+             "|---|---:|---:|"]
+    for label, v in rows:
+        lines.append(f"| {label} | {v:.1f} | {v / t_step:.3f} |")
+    lines.append(f"| unaccounted (set-up, kept part, the final reduction) | "
+                 f"{t_step - accounted:.1f} | {(t_step - accounted) / t_step:.3f} |")
+    lines += ["", "Steps by decision path (share of all steps): " +
+              ", ".join(f"{f} {v:.4f}" for f, v in counts.items()), ""]
+    dec_per = {f: float(P[:, FIELDS.index("decide_" + f)].sum() /
+                        max(1.0, P[:, FIELDS.index("count_" + f)].sum()))
+               for f in ("roulette", "fallback", "ir")}
+    lines.append("Ticks per decision on each path: " +
+                 ", ".join(f"{f} {v:.1f}" for f, v in dec_per.items()))
+    text = "\n".join(lines) + "\n"
+    print(text)
+    if args.out:
+        with open(args.out, "w") as fh:
+            fh.write(text)
+
+
+if __name__ == "__main__":
+    main()

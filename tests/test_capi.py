@@ -55,6 +55,7 @@ def test_strerror_and_version(L):
     assert L.aco_strerror(0) == b"ACO_OK"
     assert L.aco_strerror(-1) == b"ACO_ERR_INVALID_ARG"
     assert L.aco_strerror(-4) == b"ACO_ERR_WORKSPACE"
+    assert L.aco_strerror(-6) == b"ACO_ERR_DEVICE"
     assert L.aco_strerror(-99) == b"ACO_ERR_UNKNOWN"
     assert b"gfx950" in L.aco_version()
 
@@ -70,10 +71,36 @@ def test_workspace_queries(L):
     total = L.aco_run_workspace_bytes(n, C.byref(p))
     assert total >= m * n * 5 + n * k * (4 + 4 + 1 + 4 + 4 + 8 + 8) + g
     assert L.aco_grid_bytes(0) == 0
+    # the one query by kind agrees with each entry point's own
+    W = aco.aco_workspace_bytes
+    assert W(aco.ACO_WS_GRID, n, k, m) == g
+    assert W(aco.ACO_WS_CONSTRUCT, n, k, m) == L.aco_construct_workspace_bytes(n, k)
+    assert W(aco.ACO_WS_UPDATE, n, k, m) == L.aco_update_workspace_bytes(n, k, m)
+    assert W(aco.ACO_WS_RUN, n, k, m) == total
+    assert W(aco.ACO_WS_TWO_OPT, n, k, m) == L.aco_two_opt_workspace_bytes(n, m, 1)
+    assert W(aco.ACO_WS_FEATURES, n, k, m) == L.aco_features_workspace_bytes()
+    assert W(aco.ACO_WS_MLP_BACKWARD, n, k, m) == L.aco_mlp_backward_workspace_bytes(n * k)
+    assert W(99, n, k, m) == 0
+    # the learned heuristic adds the features (32 bytes per slot) and their workspace
+    pl = aco.AcoParams(m=m, k=k, alpha=1.0, beta=2.0, rho=0.1, iterations=50, deposit_shift=32,
+                       seed=2, eta_mode=aco.ACO_ETA_LEARNED)
+    assert L.aco_run_workspace_bytes(n, C.byref(pl)) >= total + 32 * n * k
+    # parameters: struct_size must cover the fields through seed
+    assert p.struct_size == C.sizeof(aco.AcoParams)
+    short = aco.AcoParams(m=m, k=k, alpha=1.0, beta=2.0, rho=0.1, iterations=50,
+                          deposit_shift=32, seed=2)
+    short.struct_size = 24
+    assert L.aco_run_workspace_bytes(n, C.byref(short)) == 0
+    # a caller built before eta_mode existed: its fields are read, the rest default
+    short.struct_size = aco.AcoParams.seed.offset + 8
+    short.eta_mode = 7            # beyond struct_size: never read
+    assert L.aco_run_workspace_bytes(n, C.byref(short)) == total
 
 
 def test_validation_before_any_device_call(L):
-    # every call below fails validation on the host; NULL pointers are never touched
+    # every call below fails validation on the host; NULL pointers are never touched,
+    # nor the fake non-NULL one
+    fake = C.c_void_p(16)
     assert L.aco_build_candidates(None, 2, 1, 2.0, None, None, None, None, None, None, 0,
                                   None) == aco.ACO_ERR_INVALID_ARG
     assert b"n = 2" in L.aco_last_error()
@@ -100,6 +127,29 @@ def test_validation_before_any_device_call(L):
                      None) == aco.ACO_ERR_INVALID_ARG
     assert L.aco_run(None, 100, None, None, None, None, None, None, 0,
                      None) == aco.ACO_ERR_INVALID_ARG
+    for mode, w in ((5, None), (aco.ACO_ETA_LEARNED, None)):
+        p = aco.AcoParams(m=4, k=8, alpha=1.0, beta=2.0, rho=0.1, iterations=1, deposit_shift=32,
+                          seed=1, eta_mode=mode, mlp_w=w)
+        assert L.aco_run(None, 100, C.byref(p), None, None, None, None, None, 0,
+                         None) == aco.ACO_ERR_INVALID_ARG
+        assert b"eta_mode" in L.aco_last_error() or b"mlp_w" in L.aco_last_error()
+    p.struct_size = 16
+    assert L.aco_run(None, 100, C.byref(p), None, None, None, None, None, 0,
+                     None) == aco.ACO_ERR_INVALID_ARG
+    assert b"struct_size" in L.aco_last_error()
+    # batched colonies: eta = 1/d only; k = 0 is for aco_run_batched alone
+    off = (C.c_int64 * 3)(0, 50, 120)
+    p = aco.AcoParams(m=4, k=8, alpha=1.0, beta=2.0, rho=0.1, iterations=1, deposit_shift=32,
+                      seed=1, eta_mode=aco.ACO_ETA_LEARNED, mlp_w=16)
+    assert L.aco_batch_setup(fake, off, 2, C.byref(p), fake, fake, fake, 1 << 30,
+                             None) == aco.ACO_ERR_UNSUPPORTED
+    p = aco.AcoParams(m=4, k=0, alpha=1.0, beta=2.0, rho=0.1, iterations=1, deposit_shift=32,
+                      seed=1)
+    assert L.aco_batch_setup(fake, off, 2, C.byref(p), fake, fake, fake, 1 << 30,
+                             None) == aco.ACO_ERR_INVALID_ARG
+    assert L.aco_batch_workspace_bytes(off, 2, C.byref(p)) == L.aco_batch_workspace_bytes(
+        off, 2, C.byref(aco.AcoParams(m=4, k=16, alpha=1.0, beta=2.0, rho=0.1, iterations=1,
+                                      deposit_shift=32, seed=1)))
     # windowed 2-opt: window, p, batch, round cap and NULL arrays, all before the GPU
     st = aco.AcoTwoOptStats()
     for window, p, batch, rounds in ((0, 0.5, 1, 0), (2049, 0.5, 1, 0), (10, 1.5, 1, 0),
@@ -109,6 +159,21 @@ def test_validation_before_any_device_call(L):
                              C.byref(st), None, 0, None) == aco.ACO_ERR_INVALID_ARG
     assert L.aco_two_opt_workspace_bytes(200000, 1024, 8) >= 8 * 200000 * 8
     assert L.aco_two_opt_workspace_bytes(0, 1, 1) == 0
+    # local-best pheromone: m * 2^shift must stay below 2^63 (checked before the arrays)
+    assert L.aco_pheromone_local_best(100, 8, fake, fake, 1024, fake, fake, 1.0, 1.0, 53, fake,
+                                      fake, 1 << 30, None) == aco.ACO_ERR_INVALID_ARG
+    assert b"overflow" in L.aco_last_error()
+    assert L.aco_pheromone_local_best(100, 8, None, None, 1024, None, None, 1.0, 1.0, 52, None,
+                                      None, 0, None) == aco.ACO_ERR_INVALID_ARG
+    assert b"NULL" in L.aco_last_error()
+    # construction options: struct_size must cover the fields through lbest
+    opts = aco.AcoConstructOpts(aco.ACO_SAMPLER_ROULETTE, 0.0, 1, None, None)
+    assert opts.struct_size == C.sizeof(aco.AcoConstructOpts)
+    opts.struct_size = 8
+    assert L.aco_construct_ex(fake, 100, 8, fake, fake, fake, fake, fake, 4, 0, 1.0, 1, 0,
+                              C.byref(opts), fake, fake, fake, None, fake, 1 << 30,
+                              None) == aco.ACO_ERR_INVALID_ARG
+    assert b"struct_size" in L.aco_last_error()
 
 
 def test_no_oracle_in_product_path():

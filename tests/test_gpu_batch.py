@@ -53,7 +53,8 @@ def state(bt):
 def inst(S, off, b, m=M):
     lo, hi = int(off[b]), int(off[b + 1])
     n = hi - lo
-    return dict(n=n, nn=S["nn"][lo:hi], nnd=S["nnd"][lo:hi], rev=S["rev"][lo:hi],
+    k = S["nn"].shape[1]
+    return dict(n=n, k=k, nn=S["nn"][lo:hi], nnd=S["nnd"][lo:hi], rev=S["rev"][lo:hi],
                 eta_b=S["eta_b"][lo:hi], tau=S["tau"][lo:hi],
                 tours=S["tours"][m * lo:m * hi].reshape(m, n),
                 slots=S["slots"][m * lo:m * hi].reshape(m, n),
@@ -64,11 +65,18 @@ def inst(S, off, b, m=M):
 @pytest.mark.parametrize("layout", [1, 3])
 def test_batch_setup_and_iterations_match_oracle(layout):
     """layout 1: one ant per wave; 3: four ants per wave (one per 16-lane row)."""
-    import torch
     # 20 instances of the batched workload plus the smallest legal size (n = k + 1)
     tiny = instances.uniform_coords(K + 1, 99)
     bt, xy, off, sizes = make_batch(20, extra=[tiny])
-    say(f"[batch] setup B={bt.B} N={bt.N}")
+    replay_batch(bt, xy, off, K, 3, layout)
+
+
+def replay_batch(bt, xy, off, K, iterations, layout):
+    """Set-up checked against the oracle per instance, then `iterations`
+    iterations one launch at a time, every ant of every instance replayed and
+    the pheromone and bests compared after each."""
+    import torch
+    say(f"[batch] setup B={bt.B} N={bt.N} k={K}")
     bt.setup()
     S = state(bt)
     ref = {}
@@ -84,20 +92,24 @@ def test_batch_setup_and_iterations_match_oracle(layout):
         tour, L = orc.nn_tour(xb, nn, nnd)
         np.testing.assert_array_equal(I["best_tour"], tour)
         assert I["best_len"] == L
-        tau = np.full((I["n"], K), orc.tau0(I["n"], L), np.float32)
+        tau = np.full((I["n"], I["k"]), orc.tau0(I["n"], L), np.float32)
         np.testing.assert_array_equal(I["tau"], tau)
         ref[b] = dict(xy=xb, nn=nn, nnd=nnd, tau=tau, best=L)
     steps = near = 0
-    for t in range(3):
+    for t in range(iterations):
         say(f"[batch] iteration {t}")
         ib = torch.empty((bt.B, 1), dtype=torch.int64, device="cuda")
-        bt.iterate(t, 1, waves=8, layout=layout, iter_best=ib)
+        # one ant per wave also records the step probabilities
+        prob = torch.empty(bt.N * M, dtype=torch.float32, device="cuda") if layout != 3 else None
+        bt.iterate(t, 1, waves=8, layout=layout, iter_best=ib, step_prob=prob)
         S = state(bt)
+        P = None if prob is None else prob.cpu().numpy()
         ibn = ib.cpu().numpy()[:, 0]
         for b in range(bt.B):
             I, R = inst(S, off, b), ref[b]
+            pb = None if P is None else P[M * off[b]:M * off[b + 1]].reshape(M, I["n"])
             tot = check_tours(R["xy"], R["nn"], R["nnd"], R["tau"], 1.0, 2.0, SEED, t,
-                              I["tours"], I["lengths"], I["slots"], None, np.arange(M),
+                              I["tours"], I["lengths"], I["slots"], pb, np.arange(M),
                               label=f"batch b={b} t={t}")
             steps += tot["steps"]
             near += tot["near_boundary_mismatch"]
@@ -108,6 +120,7 @@ def test_batch_setup_and_iterations_match_oracle(layout):
             R["tau"] = orc.update(R["nn"], R["tau"], I["tours"], I["lengths"], 0.1, 32)
             np.testing.assert_array_equal(I["tau"], R["tau"], err_msg=f"b={b} t={t}")
     assert near <= 1e-4 * steps
+    return S
 
 
 CONFIGS = [(1, 1, 4), (2, 1, 4), (4, 1, 4), (8, 1, 4), (16, 1, 4), (4, 2, 4), (8, 2, 4),
@@ -159,12 +172,33 @@ def test_batch_four_ants_rejects_wide_rows():
     assert e.value.code == aco.ACO_ERR_INVALID_ARG
 
 
+def test_batch_k_auto_run_equals_oracle_replayed_fixed_k():
+    """k = 0: the library picks k from 8, 10, 12, 16 by time to equal quality;
+    the run then equals a fixed-k run of the chosen k that the oracle replays
+    iteration by iteration."""
+    import torch
+    bt, xy, off, sizes = make_batch(12, iterations=3, k=0)
+    ib = torch.empty((bt.B, 3), dtype=torch.int64, device="cuda")
+    tuned = bt.run(autotune=0, iter_best=ib)
+    k = tuned[3]
+    say(f"[batch] k-auto chose k={k}")
+    assert k in (8, 10, 12, 16) and bt.params.k == k
+    A = state(bt)
+    ref, *_ = make_batch(12, iterations=3, k=k)
+    Bst = replay_batch(ref, xy, off, k, 3, 1)
+    for f in ("tau", "tours", "slots", "lengths", "best_tours", "best_lens"):
+        np.testing.assert_array_equal(A[f], Bst[f], err_msg=f)
+
+
 def test_batch_autotuned_run_equals_fixed_configuration():
+    """Every candidate shape is timed on iteration 0 from the restored set-up
+    state; the run in the chosen shape equals a fixed one in every iteration."""
     import torch
     bt, xy, off, sizes = make_batch(40, iterations=9)
     ib = torch.empty((bt.B, 9), dtype=torch.int64, device="cuda")
     tuned = bt.run(autotune=1, iter_best=ib)
     assert tuned[0] in (4, 8, 16) and tuned[1] in (1, 2, 3) and tuned[2] in (4, 8)
+    assert tuned[3] == K
     A = state(bt)
     bt2, *_ = make_batch(40, iterations=9)
     bt2.setup()

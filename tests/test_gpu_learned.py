@@ -1,9 +1,9 @@
 """Training the learned edge heuristic on the GPU and what it gains.
 
 The network is trained by the library's own kernels on edges of the best
-tours the batched colonies find on uniform instances; the test then runs the
-colony with plain eta = 1/d and with the learned score on a held-out
-instance for the same number of iterations and reports both."""
+tours the batched colonies find on uniform instances; the last test compares
+the colony with plain eta = 1/d and with the learned score, each at its own
+best beta chosen on held-out instances, and states what the network adds."""
 import time
 
 import numpy as np
@@ -76,18 +76,32 @@ def _run(xy, m, iterations, seed, beta, theta=None):
     return int(col.best_len.item()), mean0, time.perf_counter() - t0
 
 
-def test_learned_heuristic_gain_on_held_out_instance(data):
+def test_learned_heuristic_against_plain_eta_at_each_best_beta(data):
+    """What the network gains, measured honestly.  Each heuristic gets its own
+    best beta from {2, 4, 8, 12}, chosen on two held-out instances; then both
+    run the same iterations on a third.  Measured: at the configured beta = 2
+    the learned score builds shorter tours (its distribution is sharper), but
+    at each one's best beta plain eta = 1/d is as good: the network adds
+    nothing beyond what a larger beta gives (less than 1% either way)."""
     from paper_1709_03187_amd import learned
     tr = learned.train(data, instances.mlp_parameters(0), steps=600, batch=32768, lr=2e-3)
-    xy = instances.uniform_coords(5000, 77)
     m, its = 64, 30
-    plain, plain_mean, tp = _run(xy, m, its, 9, 2.0)
-    plain8, plain8_mean, tp8 = _run(xy, m, its, 9, 8.0)
-    lrn, lrn_mean, tl = _run(xy, m, its, 9, 8.0, theta=tr.theta)
-    gain = (plain - lrn) / plain
-    say(f"[learned] held-out n=5000, {its} iterations: plain beta=2 {plain} ({tp:.2f}s), "
-        f"plain beta=8 {plain8}, learned beta=8 {lrn} ({tl:.2f}s); gain over plain "
-        f"{100 * gain:.2f}%, over plain at the same beta {100 * (plain8 - lrn) / plain8:.2f}%; "
-        f"first-iteration mean tour {plain_mean:.0f} / {plain8_mean:.0f} / {lrn_mean:.0f}")
-    assert lrn_mean < plain_mean       # the learned score builds shorter tours ...
-    assert gain > 0                    # ... and a shorter best tour in the same iterations
+    select = [instances.uniform_coords(5000, 70 + s) for s in range(2)]
+    betas = (2.0, 4.0, 8.0, 12.0)
+    score = {}
+    for name, th in (("plain", None), ("learned", tr.theta)):
+        for beta in betas:
+            score[name, beta] = np.mean([_run(x, m, its, 9, beta, th)[0] for x in select])
+    bp = min(betas, key=lambda b: score["plain", b])
+    bl = min(betas, key=lambda b: score["learned", b])
+    xy = instances.uniform_coords(5000, 77)
+    plain2, plain_mean, _ = _run(xy, m, its, 9, 2.0)
+    lrn2, lrn_mean, _ = _run(xy, m, its, 9, 2.0, theta=tr.theta)
+    plain_best, _, tp = _run(xy, m, its, 9, bp)
+    lrn_best, _, tl = _run(xy, m, its, 9, bl, theta=tr.theta)
+    gain_best = (plain_best - lrn_best) / plain_best
+    say(f"[learned] held-out n=5000, {its} iterations: beta=2 plain {plain2} learned {lrn2}; "
+        f"best beta plain {bp:g} -> {plain_best} ({tp:.2f}s), learned {bl:g} -> {lrn_best} "
+        f"({tl:.2f}s); gain at each best beta {100 * gain_best:.2f}%")
+    assert lrn_mean < plain_mean and lrn2 < plain2   # sharper than 1/d^2 ...
+    assert abs(gain_best) < 0.01                     # ... but nothing a larger beta does not give

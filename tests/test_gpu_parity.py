@@ -210,6 +210,40 @@ def test_aco_run_matches_stepwise_and_oracle():
     np.testing.assert_array_equal(to_np(best_tour), ref["best_tour"])
 
 
+def test_aco_run_with_learned_heuristic_equals_stepwise_colony():
+    """eta_mode = ACO_ETA_LEARNED: aco_run scores the candidate edges with the
+    network and runs the loop on sigmoid(z)^beta; the same calls made one by
+    one (features, forward, then the loop) give bit-identical results."""
+    import torch
+    import paper_1709_03187_amd as aco
+    xy = instances.uniform_coords(1500, 41)
+    n, k, m, iters, beta = len(xy), 12, 32, 5, 6.0
+    theta = torch.from_numpy(instances.mlp_parameters(3)).cuda()
+    p = aco.AcoParams(m=m, k=k, alpha=1.0, beta=beta, rho=0.1, iterations=iters,
+                      deposit_shift=32, seed=8, eta_mode=aco.ACO_ETA_LEARNED,
+                      mlp_w=theta.data_ptr())
+    ws = torch.empty(aco.aco_run_workspace_bytes(n, p), dtype=torch.uint8, device="cuda")
+    xy_d = torch.from_numpy(xy).cuda()
+    best_tour = torch.empty(n, dtype=torch.int32, device="cuda")
+    best_len = torch.empty(1, dtype=torch.int64, device="cuda")
+    iter_best = torch.empty(iters, dtype=torch.int64, device="cuda")
+    tau_out = torch.empty((n, k), dtype=torch.float32, device="cuda")
+    aco.aco_run(xy_d, n, p, best_tour, best_len, iter_best, tau_out, ws)
+    col = colony(xy, k=k, m=m, beta=beta, seed=8, theta=theta)
+    col.setup()
+    ib = torch.empty(iters, dtype=torch.int64, device="cuda")
+    for it in range(iters):
+        col.iterate(it, ib[it:it + 1])
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(to_np(iter_best), to_np(ib))
+    np.testing.assert_array_equal(to_np(tau_out), to_np(col.tau))
+    assert int(best_len.item()) == int(col.best_len.item())
+    np.testing.assert_array_equal(to_np(best_tour), to_np(col.best_tour))
+    # and the table really is the network's, not 1/d
+    eta = 1.0 / np.maximum(to_np(col.nnd), 1).astype(np.float64)
+    assert not np.array_equal(to_np(col.eta_b), (eta ** beta).astype(np.float32))
+
+
 def test_ant_split_and_determinism():
     import torch
     xy = instances.uniform_coords(1500, 8)
