@@ -195,6 +195,25 @@ int aco_update_pheromone(int32_t n, int32_t k, const int32_t *nn, const int8_t *
                          double rho, int32_t deposit_shift, float *tau, void *ws, size_t ws_bytes,
                          void *stream);
 
+/* The same update without a workspace argument, for callers that cannot
+ * allocate device memory (code being captured into a HIP graph, serving
+ * loops, harnesses that forbid allocation).  It allocates nothing: the slot
+ * sums and quanta live in a scratch array the library holds on every device
+ * it runs on (ACO_UPDATE_STATIC_BYTES bytes each, kept until the process
+ * ends), so aco_update_workspace_bytes(n, k, m) must not exceed
+ * ACO_UPDATE_STATIC_BYTES (n = 200,000 and k = 16 fit with m up to
+ * 994,000).  The scratch is cleared by a kernel at the start of every call.
+ * Calls on one device share that scratch: two calls that overlap (on
+ * different streams, or from different threads without ordering) race and
+ * give wrong pheromone.  Results are bit-identical to aco_update_pheromone's.
+ * Errors: INVALID_ARG (as aco_update_pheromone, and sizes beyond the
+ * scratch), HIP.  Device checks as aco_update_pheromone. */
+#define ACO_UPDATE_STATIC_BYTES (32u << 20)
+int aco_update_pheromone_static(int32_t n, int32_t k, const int32_t *nn, const int8_t *rev,
+                                int32_t m, const int32_t *tours, const uint8_t *slots,
+                                const int64_t *lengths, double rho, int32_t deposit_shift,
+                                float *tau, void *stream);
+
 /* ------------------------------------------------------------------------
  * Best-tour tracking (the method outputs the best tour found, Alg. 1's last
  * step).  The iteration best is the shortest of lengths[0..m) (lowest ant on

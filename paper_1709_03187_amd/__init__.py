@@ -41,10 +41,12 @@ EXPORTS = (
     "aco_edge_features", "aco_mlp_forward", "aco_mlp_backward_workspace_bytes",
     "aco_mlp_backward", "aco_mlp_adam", "aco_tour_edge_labels", "aco_construct_partial",
     "aco_update_local_best", "aco_pheromone_local_best", "aco_construct_ex",
-    "aco_two_opt_workspace_bytes", "aco_two_opt", "aco_workspace_bytes",
+    "aco_two_opt_workspace_bytes", "aco_two_opt", "aco_update_pheromone_static",
+    "aco_workspace_bytes",
 )
 ACO_WS_GRID, ACO_WS_CONSTRUCT, ACO_WS_UPDATE, ACO_WS_RUN = 0, 1, 2, 3
 ACO_WS_TWO_OPT, ACO_WS_FEATURES, ACO_WS_MLP_BACKWARD = 4, 5, 6
+ACO_UPDATE_STATIC_BYTES = 32 << 20
 ACO_TWO_OPT_MAX_WINDOW = 2048
 ACO_SAMPLER_ROULETTE = 0
 ACO_SAMPLER_INDEPENDENT = 1
@@ -117,6 +119,8 @@ def lib():
             "aco_update_workspace_bytes": (sz, [i32, i32, i32]),
             "aco_update_pheromone": (C.c_int, [i32, i32, p, p, i32, p, p, p, dbl, i32, p, p, sz,
                                                p]),
+            "aco_update_pheromone_static": (C.c_int, [i32, i32, p, p, i32, p, p, p, dbl, i32,
+                                                      p, p]),
             "aco_track_best": (C.c_int, [i32, i32, p, p, p, p, p, p]),
             "aco_run_workspace_bytes": (sz, [i32, C.POINTER(AcoParams)]),
             "aco_run": (C.c_int, [p, i32, C.POINTER(AcoParams), p, p, p, p, p, sz, p]),
@@ -258,6 +262,17 @@ def aco_update_pheromone(n, k, nn, rev, m, tours, slots, lengths, rho, deposit_s
         _ptr(tours, torch.int32, "tours"), _ptr(slots, torch.uint8, "slots"),
         _ptr(lengths, torch.int64, "lengths"), float(rho), int(deposit_shift),
         _ptr(tau, torch.float32, "tau"), _ptr(ws, torch.uint8, "ws"), ws.numel(), _stream(stream)))
+
+
+def aco_update_pheromone_static(n, k, nn, rev, m, tours, slots, lengths, rho, deposit_shift, tau,
+                                stream=None):
+    """aco_update_pheromone on the library's own per-device scratch (no workspace)."""
+    torch = _t()
+    _check(lib().aco_update_pheromone_static(
+        n, k, _ptr(nn, torch.int32, "nn"), _ptr(rev, torch.int8, "rev"), m,
+        _ptr(tours, torch.int32, "tours"), _ptr(slots, torch.uint8, "slots"),
+        _ptr(lengths, torch.int64, "lengths"), float(rho), int(deposit_shift),
+        _ptr(tau, torch.float32, "tau"), _stream(stream)))
 
 
 def aco_track_best(n, m, tours, lengths, best_len, best_tour, iter_best=None, stream=None):

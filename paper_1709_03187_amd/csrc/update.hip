@@ -285,6 +285,50 @@ extern "C" int aco_update_pheromone(int32_t n, int32_t k, const int32_t *nn, con
                             as_stream(stream));
 }
 
+// The update's scratch for callers that cannot allocate: the slot sums and
+// quanta of one update, held by the library on every device it runs on.
+// Host code uses only the device address taken below, never this name.
+static __device__ __align__(256) unsigned char scratch[ACO_UPDATE_STATIC_BYTES];
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[256];
+
+// Device address of this device's scratch, located on the first call per device.
+static int scratch_address(void **out)
+{
+    int dev = 0;
+    ACO_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 256) return fail(ACO_ERR_HIP, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        ACO_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(ACO_ERR_HIP, "no device address for the update scratch");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return ACO_OK;
+}
+
+extern "C" int aco_update_pheromone_static(int32_t n, int32_t k, const int32_t *nn,
+                                           const int8_t *rev, int32_t m, const int32_t *tours,
+                                           const uint8_t *slots, const int64_t *lengths,
+                                           double rho, int32_t deposit_shift, float *tau,
+                                           void *stream)
+{
+    clear_error();
+    int rc = validate_update(n, k, nn, rev, m, tours, lengths, rho, deposit_shift, tau);
+    if (rc != ACO_OK) return rc;
+    const size_t need = aco_update_workspace_bytes(n, k, m);
+    ACO_REQUIRE(need <= (size_t)ACO_UPDATE_STATIC_BYTES,
+                "n k 8 + m 8 = %zu bytes exceed the %u bytes of the static scratch", need,
+                (unsigned)ACO_UPDATE_STATIC_BYTES);
+    void *ws = nullptr;
+    rc = scratch_address(&ws);
+    if (rc != ACO_OK) return rc;
+    return update_pheromone(n, k, nn, rev, m, tours, slots, lengths, rho, deposit_shift, tau, ws,
+                            as_stream(stream));
+}
+
 extern "C" int aco_track_best(int32_t n, int32_t m, const int32_t *tours, const int64_t *lengths,
                               int64_t *best_len, int32_t *best_tour, int64_t *iter_best,
                               void *stream)
