@@ -148,6 +148,10 @@ int aco_init_pheromone(const int32_t *xy, int32_t n, int32_t k, const int32_t *n
  * candidate has positive weight the ant moves to the nearest unvisited city
  * (smallest (d, j)), found exactly on the grid.
  *
+ *   nn, nnd, eta_b, grid   as written by aco_build_candidates (eta_b possibly
+ *            replaced by a learned table); the kernels take the candidate
+ *            lists from the grid's table by position, which holds the same
+ *            lists as nn, so nn must be the lists this grid was built with
  *   tau      float [n][k]  pheromone (read)
  *   ant0     index of the first ant (ants ant0..ant0+m-1 are built; the
  *            Philox counter uses the absolute ant index)

@@ -213,10 +213,11 @@ __device__ __forceinline__ bool possible_tour_length(int64_t L, int32_t n)
 
 // Step profile (a separate build with ACO_STEP_PROFILE defined; the library
 // itself is built without it).  Each ant's wave stamps the shader clock
-// (s_memtime) at three points of every construction step: once the row of
-// the current city has arrived, once the next city is known, and at the end
-// of the step (and once per block of 64 steps); the stamps are read only at
-// later LDS waits, so they add no wait of their own.  Per ant (16 counters,
+// (s_memtime) at four points of every construction step: once the row of
+// the current city has arrived, once its visited test is known, once the
+// next city is known, and at the end of the step (and once per block of 64
+// steps); the stamps are added up one step later, after the next visited
+// test's LDS wait.  Per ant (16 counters,
 // lane 0 writes them at the end):
 enum StepProfile {
     kProfTotal = 0,      // clock ticks of the whole build_ant call
@@ -225,11 +226,12 @@ enum StepProfile {
     kProfTail = 2,       // next city known until the end of the step (miss load
                          // issue, visited bit, staging)
     kProfBlock = 3,      // between blocks: Philox words, stores, tour entries
-    kProfDecide = 4,     // row arrived until next city known, by path (+0..2):
+    kProfDecide = 4,     // visited test done until next city known, by path (+0..2):
                          // roulette scan, nearest-unvisited fallback,
                          // Independent Roulette
     kProfCount = 7,      // steps by the same paths (+0..2)
     kProfSteps = 10,     // steps
+    kProfVisited = 11,   // row arrived until the visited test's ballot is known
     kProfFields = 16
 };
 #ifdef ACO_STEP_PROFILE
@@ -241,7 +243,7 @@ enum StepProfile {
 // The counters of one ant, held in scalar registers (no indexed array, which
 // would live in scratch memory).
 struct StepCounters {
-    uint64_t total = 0, row = 0, tail = 0, block = 0, steps = 0;
+    uint64_t total = 0, row = 0, tail = 0, block = 0, steps = 0, visited = 0;
     uint64_t dec[3] = {}, cnt[3] = {};
     __device__ __forceinline__ void decided(int path, uint64_t dt)
     {
@@ -264,6 +266,7 @@ struct StepCounters {
             out[kProfCount + p] = cnt[p];
         }
         out[kProfSteps] = steps;
+        out[kProfVisited] = visited;
     }
 };
 
@@ -296,7 +299,7 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
     // (stamps of the previous step, added up once its results are known to
     // have arrived: after the next LDS wait, so that no wait is added)
     ACO_PROF(StepCounters pc; const uint64_t t_start = __builtin_amdgcn_s_memtime();
-             uint64_t t_last = t_start, q0 = 0, q1 = 0, q2 = 0, q3 = 0; int qpath = -1;)
+             uint64_t t_last = t_start, q0 = 0, q1 = 0, q1b = 0, q2 = 0, q3 = 0; int qpath = -1;)
 
     const GridView g = grid();              // read once: no state carried through the loop
     uint32_t rnd = colony_draw(T.seed, T.iteration, T.ant, (uint32_t)lane);
@@ -497,9 +500,11 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
             // lane mask re-materialised in a vector register)
             const uint64_t any = __builtin_amdgcn_ballot_w64(seen == 0u) &
                                  __builtin_amdgcn_ballot_w64(e.w > 0.0f) & act_mask;
-            ACO_PROF(if (qpath >= 0) {
+            ACO_PROF(asm volatile("" ::"s"(any)); const uint64_t t1b = __builtin_amdgcn_s_memtime();
+                     if (qpath >= 0) {
                 pc.row += q1 - q0;
-                pc.decided(qpath, q2 - q1);
+                pc.visited += q1b - q1;
+                pc.decided(qpath, q2 - q1b);
                 pc.tail += q3 - q2;
             })
             // the first candidate that can be chosen is the likeliest next city
@@ -566,7 +571,7 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
             }
             c = jn;
             ACO_PROF(const uint64_t t3 = __builtin_amdgcn_s_memtime(); t_last = t3; q0 = t0;
-                     q1 = t1; q2 = t2; q3 = t3; qpath = path;)
+                     q1 = t1; q1b = t1b; q2 = t2; q3 = t3; qpath = path;)
         }
         // records go out now; the tour entries need a load (city index and
         // coordinates by position), so they go out one block later, when that
@@ -597,7 +602,8 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
     if (next_bad && lane == 0) flag_error(T.err, kErrNextCity);
     ACO_PROF(if (qpath >= 0) {
         pc.row += q1 - q0;
-        pc.decided(qpath, q2 - q1);
+        pc.visited += q1b - q1;
+        pc.decided(qpath, q2 - q1b);
         pc.tail += q3 - q2;
     } if (T.prof && lane == 0) {
         pc.total = __builtin_amdgcn_s_memtime() - t_start;

@@ -87,7 +87,6 @@ __device__ void build_ants4(const Ants4Task &T, unsigned char *lds, size_t set_b
 
     CandW eg = T.rows[(int64_t)c * k + lr], en = eg;
     bool hit = true;
-    bool next_bad = false;
     for (int32_t base = 0; base < n; base += kWave) {
         if (base > 0) fill_draws(base);
         const int32_t last = min(base + kWave - 1, n - 1);
@@ -134,10 +133,11 @@ __device__ void build_ants4(const Ants4Task &T, unsigned char *lds, size_t set_b
                                                  [&](int city) { return vp.test(city); });
                 jn = q == p ? jp : jn;
             }
-            // always in range; the guard keeps a logic error in bounds (reported
-            // once the tours are done)
+            // always in range; the guard keeps a logic error in bounds and
+            // reports it (a branch that is never taken: no register held
+            // across the loop, which would cost spills at this occupancy)
             const bool out = (uint32_t)jn >= (uint32_t)n;
-            next_bad |= __builtin_amdgcn_ballot_w64(out && mine) != 0ull;
+            if (__builtin_expect(out && mine, 0)) flag_error(T.err, kErrNextCity);
             jn = out ? start : jn;
             hit = jn == guess;
             if (!hit) en = T.rows[(int64_t)jn * k + lr];
@@ -157,7 +157,6 @@ __device__ void build_ants4(const Ants4Task &T, unsigned char *lds, size_t set_b
             }
         }
     }
-    if (next_bad && lane == 0) flag_error(T.err, kErrNextCity);
 }
 
 }  // namespace aco

@@ -21,22 +21,20 @@ namespace aco {
 
 // Choice weights of every row, by position in cell order: the row of city i
 // is row pinv[i] of the table, its candidates named by position.  One thread
-// per city in index order, so nn, tau and eta_b are read as streams; each
-// thread writes its whole row (one 128-byte line at k = 16).
-struct ToPosition {
-    const int32_t *pinv;
-    __device__ __forceinline__ int32_t operator()(int32_t c) const { return pinv[c]; }
-};
-
-__global__ void k_choice_info(const int32_t *__restrict__ pinv, const int32_t *__restrict__ nn,
-                              const float *__restrict__ tau, const float *__restrict__ eta_b,
-                              int32_t n, int32_t k, double alpha, CandW *__restrict__ rows)
+// per city in index order, so tau and eta_b are read as streams; the
+// candidates by position are the first k entries of the grid's neighbour
+// table by position (the same (d, index)-ordered list the candidate list is
+// a prefix of), one 64-byte read per row at k = 16 instead of k gathers of
+// pinv; each thread writes its whole row (one 128-byte line at k = 16).
+__global__ void k_choice_info(const int32_t *__restrict__ pinv, const int32_t *__restrict__ ext_pos,
+                              int32_t kxp, const float *__restrict__ tau,
+                              const float *__restrict__ eta_b, int32_t n, int32_t k, double alpha,
+                              CandW *__restrict__ rows)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int64_t rb = i * k;
-    choice_row(nn + rb, tau + rb, eta_b + rb, k, alpha, rows + (int64_t)pinv[i] * k,
-               ToPosition{pinv});
+    const int64_t q = pinv[i], rb = i * k;
+    choice_row(ext_pos + q * kxp, tau + rb, eta_b + rb, k, alpha, rows + q * k);
 }
 
 struct ConstructArgs {
@@ -150,7 +148,9 @@ static int construct(const int32_t *xy, int32_t n, int32_t k, const int32_t *nn,
     CandW *rows = (CandW *)ws;
     const GridLayout lay(n);
     const int32_t *pinv = (const int32_t *)((const char *)grid + lay.pinv);
-    k_choice_info<<<blocks_for(n, 256), 256, 0, st>>>(pinv, nn, tau, eta_b, n, k, alpha, rows);
+    const int32_t *ext_pos = (const int32_t *)((const char *)grid + lay.ext_pos);
+    k_choice_info<<<blocks_for(n, 256), 256, 0, st>>>(pinv, ext_pos, ext_pos_width(n), tau, eta_b,
+                                                        n, k, alpha, rows);
     ACO_LAUNCH_CHECK("k_choice_info");
     void (*kern)(ConstructArgs);
     if (sampler == ACO_SAMPLER_INDEPENDENT)   // no step probabilities (checked above)

@@ -26,7 +26,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 PROFILE_LIB = os.path.join(HERE, "libaco_step_profile.so")
 FIELDS = ["total", "row_wait", "tail", "block", "decide_roulette", "decide_fallback",
-          "decide_ir", "count_roulette", "count_fallback", "count_ir", "steps"]
+          "decide_ir", "count_roulette", "count_fallback", "count_ir", "steps", "visited"]
 NFIELDS = 16
 
 
@@ -73,15 +73,16 @@ def main():
     steps = P[:, FIELDS.index("steps")]
     total = P[:, 0]
     ticks_per_ms = total.max() / construct_ms
-    per_step = {f: float((P[:, i] / steps).mean()) for i, f in enumerate(FIELDS[:7])}
+    per_step = {f: float((P[:, i] / steps).mean()) for i, f in enumerate(FIELDS)
+                if not f.startswith("count_") and f != "steps"}
     counts = {f[6:]: float(P[:, FIELDS.index(f)].sum() / steps.sum())
               for f in FIELDS if f.startswith("count_")}
     t_step = per_step["total"]
     rows = [("row wait (end of the previous step until the current row has arrived)",
              per_step["row_wait"]),
-            ("decision: visited test, guess load issue, FP64 scan, pick",
-             per_step["decide_roulette"]),
-            ("decision: nearest-unvisited fallback (visited test, table, grid)",
+            ("visited test of the row's candidates (LDS read, ballot)", per_step["visited"]),
+            ("decision: guess load issue, FP64 scan, pick", per_step["decide_roulette"]),
+            ("decision: nearest-unvisited fallback (table rows, grid search)",
              per_step["decide_fallback"]),
             ("decision: Independent Roulette", per_step["decide_ir"]),
             ("rest of the step (miss load issue, visited bit, staging)", per_step["tail"]),
