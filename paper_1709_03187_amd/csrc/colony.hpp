@@ -217,8 +217,9 @@ __device__ __forceinline__ bool possible_tour_length(int64_t L, int32_t n)
 // the current city has arrived, once its visited test is known, once the
 // next city is known, and at the end of the step (and once per block of 64
 // steps); the stamps are added up one step later, after the next visited
-// test's LDS wait.  Per ant (16 counters,
-// lane 0 writes them at the end):
+// test's LDS wait.  Fallback decisions are also counted by duration (a
+// table chunk costs about one row load, a grid search several).  Per ant (16
+// counters, lane 0 writes them at the end):
 enum StepProfile {
     kProfTotal = 0,      // clock ticks of the whole build_ant call
     kProfRowWait = 1,    // end of the previous step (or block top) until the row of
@@ -232,8 +233,11 @@ enum StepProfile {
     kProfCount = 7,      // steps by the same paths (+0..2)
     kProfSteps = 10,     // steps
     kProfVisited = 11,   // row arrived until the visited test's ballot is known
+    kProfFbMid = 12,     // fallback decisions of kFbMidTicks..kFbLongTicks: count, ticks (+1)
+    kProfFbLong = 14,    // fallback decisions of kFbLongTicks or more: count, ticks (+1)
     kProfFields = 16
 };
+constexpr uint64_t kFbMidTicks = 2000, kFbLongTicks = 6000;
 #ifdef ACO_STEP_PROFILE
 #define ACO_PROF(...) __VA_ARGS__
 #else
@@ -253,6 +257,15 @@ struct StepCounters {
             cnt[p] += path == p ? 1 : 0;
         }
         ++steps;
+    }
+    // long fallback decisions go straight to the (zeroed) output, so that the
+    // step loop carries no more registers; the store below leaves them alone
+    __device__ __forceinline__ static void long_fallback(uint64_t *out, uint64_t dt)
+    {
+        if (!out || dt < kFbMidTicks) return;
+        const int f = dt >= kFbLongTicks ? kProfFbLong : kProfFbMid;
+        atomicAdd((unsigned long long *)&out[f], 1ull);
+        atomicAdd((unsigned long long *)&out[f + 1], (unsigned long long)dt);
     }
     __device__ __forceinline__ void store(uint64_t *out) const
     {
@@ -505,6 +518,7 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
                 pc.row += q1 - q0;
                 pc.visited += q1b - q1;
                 pc.decided(qpath, q2 - q1b);
+                if (qpath == 1 && lane == 0) StepCounters::long_fallback(T.prof, q2 - q1b);
                 pc.tail += q3 - q2;
             })
             // the first candidate that can be chosen is the likeliest next city

@@ -395,35 +395,46 @@ __global__ __launch_bounds__(256) void k_mlp_backward(const float *feat, const u
     if (threadIdx.x == 0) loss_partial[blockIdx.x] = lred[0];
 }
 
-// Sum of the workgroups' partial rows, 64 parameters per block: thread
-// (q, p) adds rows q, q + 4, q + 8, ... with four interleaved accumulators,
-// then the four quarter sums are added in order q = 0..3.  The order depends
-// only on the number of rows, so results are reproducible.
-__global__ __launch_bounds__(256) void k_mlp_reduce(const float *partial,
-                                                    const double *loss_partial, int blocks,
-                                                    double inv_e, float *grad, double *loss)
+// Sum of the workgroups' partial rows, 64 parameters per block of 16 waves:
+// wave q adds rows q, q + 16, q + 32, ... (at most 16 rows for the largest
+// grid, all loads independent, four interleaved accumulators); the 16 wave
+// sums are then added in order q = 0..15.  The loss partials are added by the
+// first wave of block 0: lane l adds rows l, l + 64, ... in order, then a
+// fixed butterfly.  The order depends only on the number of rows, so results
+// are reproducible.
+constexpr int kReduceWaves = 16;
+__global__ __launch_bounds__(64 * kReduceWaves) void k_mlp_reduce(const float *partial,
+                                                                  const double *loss_partial,
+                                                                  int blocks, double inv_e,
+                                                                  float *grad, double *loss)
 {
-    __shared__ float part[4][64];
+    __shared__ float part[kReduceWaves][64];
     const int pl = threadIdx.x & 63, q = threadIdx.x >> 6;
     const int p = blockIdx.x * 64 + pl;
     float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
     if (p < kNParam) {
+        constexpr int S = kReduceWaves;
         int b = q;
-        for (; b + 12 < blocks; b += 16) {
+        for (; b + 3 * S < blocks; b += 4 * S) {
             a0 += partial[(int64_t)b * kNParam + p];
-            a1 += partial[(int64_t)(b + 4) * kNParam + p];
-            a2 += partial[(int64_t)(b + 8) * kNParam + p];
-            a3 += partial[(int64_t)(b + 12) * kNParam + p];
+            a1 += partial[(int64_t)(b + S) * kNParam + p];
+            a2 += partial[(int64_t)(b + 2 * S) * kNParam + p];
+            a3 += partial[(int64_t)(b + 3 * S) * kNParam + p];
         }
-        for (; b < blocks; b += 4) a0 += partial[(int64_t)b * kNParam + p];
+        for (; b < blocks; b += S) a0 += partial[(int64_t)b * kNParam + p];
     }
     part[q][pl] = (a0 + a1) + (a2 + a3);
-    __syncthreads();
-    if (q == 0 && p < kNParam) grad[p] = ((part[0][pl] + part[1][pl]) + part[2][pl]) + part[3][pl];
-    if (blockIdx.x == 0 && threadIdx.x == 0 && loss) {
+    if (blockIdx.x == 0 && q == 0 && loss) {
         double t = 0.0;
-        for (int b = 0; b < blocks; ++b) t += loss_partial[b];
-        *loss = t * inv_e;
+        for (int b = pl; b < blocks; b += 64) t += loss_partial[b];
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+        if (pl == 0) *loss = t * inv_e;
+    }
+    __syncthreads();
+    if (q == 0 && p < kNParam) {
+        float t = part[0][pl];
+        for (int w = 1; w < kReduceWaves; ++w) t += part[w][pl];
+        grad[p] = t;
     }
 }
 
@@ -567,8 +578,8 @@ extern "C" int aco_mlp_backward(const float *feat, const uint8_t *labels, int64_
     hipLaunchKernelGGL(k_mlp_backward, dim3(G), dim3(64 * kWaves), 0, st, feat, labels, E, theta,
                        pos_weight, (float)(1.0 / (double)E), partial, lpart);
     ACO_LAUNCH_CHECK("k_mlp_backward");
-    hipLaunchKernelGGL(k_mlp_reduce, dim3((kNParam + 63) / 64), dim3(256), 0, st, partial, lpart,
-                       G, 1.0 / (double)E, grad, loss);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((kNParam + 63) / 64), dim3(64 * kReduceWaves), 0, st,
+                       partial, lpart, G, 1.0 / (double)E, grad, loss);
     ACO_LAUNCH_CHECK("k_mlp_reduce");
     return ACO_OK;
 }

@@ -5,10 +5,11 @@
 
 Runs the n = 200,000 clustered workload (m = 1,024, k = 16) on
 libaco_step_profile.so, whose construction kernels stamp the shader clock at
-three points of every step (top of the step; the current row has arrived;
-the next city is known) and keep per-ant sums.  The last iteration's counters
-are summarised per ant-step: row wait, the decision by path (roulette scan,
-nearest-unvisited fallback), the rest of the step, and the work between
+four points of every step (the current row has arrived; its visited test is
+known; the next city is known; the end of the step) and keep per-ant sums.
+The last iteration's counters are summarised per ant-step: row wait, the
+visited test, the decision by path (roulette scan, nearest-unvisited
+fallback, split by duration), the rest of the step, and the work between
 blocks of 64 steps.  The tours are those of the
 library (the stamps change no result); the clock adds a few instructions per
 step, so the profiled kernel runs somewhat slower than the library's.
@@ -26,7 +27,9 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 PROFILE_LIB = os.path.join(HERE, "libaco_step_profile.so")
 FIELDS = ["total", "row_wait", "tail", "block", "decide_roulette", "decide_fallback",
-          "decide_ir", "count_roulette", "count_fallback", "count_ir", "steps", "visited"]
+          "decide_ir", "count_roulette", "count_fallback", "count_ir", "steps", "visited",
+          "fb_mid_n", "fb_mid_t", "fb_long_n", "fb_long_t"]
+FB_MID_TICKS, FB_LONG_TICKS = 2000, 6000   # the kernel's duration classes
 NFIELDS = 16
 
 
@@ -74,7 +77,7 @@ def main():
     total = P[:, 0]
     ticks_per_ms = total.max() / construct_ms
     per_step = {f: float((P[:, i] / steps).mean()) for i, f in enumerate(FIELDS)
-                if not f.startswith("count_") and f != "steps"}
+                if not f.startswith("count_") and f != "steps" and not f.endswith("_n")}
     counts = {f[6:]: float(P[:, FIELDS.index(f)].sum() / steps.sum())
               for f in FIELDS if f.startswith("count_")}
     t_step = per_step["total"]
@@ -113,6 +116,20 @@ def main():
                for f in ("roulette", "fallback", "ir")}
     lines.append("Ticks per decision on each path: " +
                  ", ".join(f"{f} {v:.1f}" for f, v in dec_per.items()))
+    # fallback decisions by duration: below FB_MID_TICKS (settled by the first
+    # table chunk), up to FB_LONG_TICKS (later chunks), above (grid search)
+    fb_n = P[:, FIELDS.index("count_fallback")].sum()
+    fb_t = P[:, FIELDS.index("decide_fallback")].sum()
+    mid_n, mid_t = P[:, FIELDS.index("fb_mid_n")].sum(), P[:, FIELDS.index("fb_mid_t")].sum()
+    lng_n, lng_t = P[:, FIELDS.index("fb_long_n")].sum(), P[:, FIELDS.index("fb_long_t")].sum()
+    all_steps = steps.sum()
+    lines += ["", "Fallback decisions by duration (ticks):", "",
+              "| class | share of steps | mean ticks | ticks per ant-step |", "|---|---:|---:|---:|"]
+    for label, cn, ct in ((f"< {FB_MID_TICKS}", fb_n - mid_n - lng_n, fb_t - mid_t - lng_t),
+                          (f"{FB_MID_TICKS}-{FB_LONG_TICKS}", mid_n, mid_t),
+                          (f">= {FB_LONG_TICKS}", lng_n, lng_t)):
+        lines.append(f"| {label} | {cn / all_steps:.4f} | {ct / max(1.0, cn):.0f} | "
+                     f"{ct / all_steps:.1f} |")
     text = "\n".join(lines) + "\n"
     print(text)
     if args.out:
