@@ -20,6 +20,18 @@ struct SameCity {
     __device__ __forceinline__ int32_t operator()(int32_t c) const { return c; }
 };
 
+// The two forms of one element's unscaled weight: the product (alpha in
+// {0, 1}) and its base-2 logarithm (other alpha; -inf for a zero factor).
+__device__ __forceinline__ double choice_product(double alpha, float t, float eb)
+{
+    return (alpha == 1.0 ? (double)t : 1.0) * (double)eb;
+}
+__device__ __forceinline__ double choice_log2(double alpha, float t, float eb)
+{
+    const double td = (double)t, ed = (double)eb;
+    return (td > 0.0 && ed > 0.0) ? alpha * log2(td) + log2(ed) : -INFINITY;
+}
+
 template <class CityMap = SameCity>
 __device__ __forceinline__ void choice_row(const int32_t *__restrict__ nn,
                                            const float *__restrict__ tau,
@@ -29,27 +41,52 @@ __device__ __forceinline__ void choice_row(const int32_t *__restrict__ nn,
     if (alpha == 1.0 || alpha == 0.0) {
         double mx = 0.0;
         for (int r = 0; r < k; ++r) {
-            const double p = (alpha == 1.0 ? (double)tau[r] : 1.0) * (double)eta_b[r];
+            const double p = choice_product(alpha, tau[r], eta_b[r]);
             mx = p > mx ? p : mx;
         }
         const int e = (mx > 0.0) ? -ilogb(mx) : 0;
-        for (int r = 0; r < k; ++r) {
-            const double p = (alpha == 1.0 ? (double)tau[r] : 1.0) * (double)eta_b[r];
-            rows[r] = CandW{map(nn[r]), (float)ldexp(p, e)};
-        }
+        for (int r = 0; r < k; ++r)
+            rows[r] = CandW{map(nn[r]), (float)ldexp(choice_product(alpha, tau[r], eta_b[r]), e)};
     } else {
         double mx = -INFINITY;
         for (int r = 0; r < k; ++r) {
-            const double t = (double)tau[r], eb = (double)eta_b[r];
-            const double lw = (t > 0.0 && eb > 0.0) ? alpha * log2(t) + log2(eb) : -INFINITY;
+            const double lw = choice_log2(alpha, tau[r], eta_b[r]);
             mx = lw > mx ? lw : mx;
         }
         for (int r = 0; r < k; ++r) {
-            const double t = (double)tau[r], eb = (double)eta_b[r];
-            const double lw = (t > 0.0 && eb > 0.0) ? alpha * log2(t) + log2(eb) : -INFINITY;
+            const double lw = choice_log2(alpha, tau[r], eta_b[r]);
             rows[r] = CandW{map(nn[r]), (float)((mx > -INFINITY) ? exp2(lw - mx) : 0.0)};
         }
     }
+}
+
+// The same weights with one lane per element: the row's elements sit in an
+// aligned group of KP lanes (KP a power of two >= k), lanes r >= k (act
+// false) hold no element.  The row maximum is exact in any order, so the
+// weights are those of choice_row bit for bit.  Every lane of the wave must
+// call it (the maximum is taken with cross-lane moves).
+template <int KP>
+__device__ __forceinline__ float choice_weight_lane(bool act, float t, float eb, double alpha)
+{
+    if (alpha == 1.0 || alpha == 0.0) {
+        const double p = act ? choice_product(alpha, t, eb) : 0.0;
+        double mx = p;
+#pragma unroll
+        for (int off = KP / 2; off > 0; off >>= 1) {
+            const double o = __shfl_xor(mx, off);
+            mx = o > mx ? o : mx;
+        }
+        const int e = (mx > 0.0) ? -ilogb(mx) : 0;
+        return (float)ldexp(p, e);
+    }
+    const double lw = act ? choice_log2(alpha, t, eb) : -INFINITY;
+    double mx = lw;
+#pragma unroll
+    for (int off = KP / 2; off > 0; off >>= 1) {
+        const double o = __shfl_xor(mx, off);
+        mx = o > mx ? o : mx;
+    }
+    return (float)((mx > -INFINITY) ? exp2(lw - mx) : 0.0);
 }
 
 // Visited sets of one ant in LDS: one bit per city, or one byte per city

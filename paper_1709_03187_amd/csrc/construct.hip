@@ -20,21 +20,35 @@
 namespace aco {
 
 // Choice weights of every row, by position in cell order: the row of city i
-// is row pinv[i] of the table, its candidates named by position.  One thread
-// per city in index order, so tau and eta_b are read as streams; the
-// candidates by position are the first k entries of the grid's neighbour
-// table by position (the same (d, index)-ordered list the candidate list is
-// a prefix of), one 64-byte read per row at k = 16 instead of k gathers of
-// pinv; each thread writes its whole row (one 128-byte line at k = 16).
-__global__ void k_choice_info(const int32_t *__restrict__ pinv, const int32_t *__restrict__ ext_pos,
-                              int32_t kxp, const float *__restrict__ tau,
-                              const float *__restrict__ eta_b, int32_t n, int32_t k, double alpha,
-                              CandW *__restrict__ rows)
+// is row pinv[i] of the table, its candidates named by position (the first k
+// entries of the grid's neighbour table by position, the same (d, index)-
+// ordered list the candidate list is a prefix of).  One lane per element, an
+// aligned group of KP lanes per row, rows in city order: tau and eta_b are
+// read as streams, each row's candidates as one contiguous read, and each
+// row is written whole by its group (one 128-byte line at k = 16).
+template <int KP>
+__global__ __launch_bounds__(256) void k_choice_info(const int32_t *__restrict__ pinv,
+                                                     const int32_t *__restrict__ ext_pos,
+                                                     int32_t kxp, const float *__restrict__ tau,
+                                                     const float *__restrict__ eta_b, int32_t n,
+                                                     int32_t k, double alpha,
+                                                     CandW *__restrict__ rows)
 {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t q = pinv[i], rb = i * k;
-    choice_row(ext_pos + q * kxp, tau + rb, eta_b + rb, k, alpha, rows + q * k);
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t i = t / KP;
+    const int r = (int)(t % KP);
+    const bool act = i < n && r < k;
+    int64_t q = 0;
+    int32_t pos = 0;
+    float tv = 0.0f, ev = 0.0f;
+    if (act) {
+        q = pinv[i];
+        pos = ext_pos[q * kxp + r];
+        tv = tau[i * k + r];
+        ev = eta_b[i * k + r];
+    }
+    const float w = choice_weight_lane<KP>(act, tv, ev, alpha);   // every lane takes part
+    if (act) rows[q * k + r] = CandW{pos, w};
 }
 
 struct ConstructArgs {
@@ -149,9 +163,14 @@ static int construct(const int32_t *xy, int32_t n, int32_t k, const int32_t *nn,
     const GridLayout lay(n);
     const int32_t *pinv = (const int32_t *)((const char *)grid + lay.pinv);
     const int32_t *ext_pos = (const int32_t *)((const char *)grid + lay.ext_pos);
-    k_choice_info<<<blocks_for(n, 256), 256, 0, st>>>(pinv, ext_pos, ext_pos_width(n), tau, eta_b,
-                                                        n, k, alpha, rows);
-    ACO_LAUNCH_CHECK("k_choice_info");
+    {
+        const int kp = k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : 64;
+        auto ci = k <= 8 ? k_choice_info<8> : k <= 16 ? k_choice_info<16>
+                : k <= 32 ? k_choice_info<32> : k_choice_info<64>;
+        ci<<<blocks_for((int64_t)n * kp, 256), 256, 0, st>>>(pinv, ext_pos, ext_pos_width(n), tau,
+                                                              eta_b, n, k, alpha, rows);
+        ACO_LAUNCH_CHECK("k_choice_info");
+    }
     void (*kern)(ConstructArgs);
     if (sampler == ACO_SAMPLER_INDEPENDENT)   // no step probabilities (checked above)
         kern = k <= 8 ? k_construct<8, 1, false> : k <= 16 ? k_construct<16, 1, false>
