@@ -162,6 +162,9 @@ int aco_init_pheromone(const int32_t *xy, int32_t n, int32_t k, const int32_t *n
  *   step_prob float [m][n] (output, may be NULL) probability of the move
  *            taken at step t (-1 for a fallback move; 1 at t = 0)
  *   ws       device workspace of aco_construct_workspace_bytes(n, k) bytes
+ *            (the choice rows: n rows of 16, 32 or 64 elements of 8 bytes
+ *            for k <= 16, <= 32, <= 64, so that each row starts on a
+ *            128-byte line)
  * Constraints: 0 <= iteration < 2^32, m >= 1, alpha >= 0 finite.
  * Errors: INVALID_ARG, WORKSPACE, UNSUPPORTED (bitmask does not fit in LDS).
  * ------------------------------------------------------------------------ */

@@ -43,7 +43,7 @@ struct BatchState {
     int32_t *nn, *nnd;     // [N][k], local indices
     int8_t *rev;           // [N][k]
     float *eta_b, *tau;    // [N][k]
-    CandW *rows;           // [N][k]
+    CandW *rows;           // [N][row_stride(k)]
     int64_t *acc;          // [N][k]
     int32_t *tours;        // instance b at m off[b]: [m][n_b]
     uint8_t *slots;        // idem
@@ -259,7 +259,8 @@ __global__ __launch_bounds__(kWave) void k_b_init(BatchState S, double alpha,
     __syncthreads();   // the rows below read tau written by other lanes
     for (int i = lane; i < n; i += kWave) {
         const int64_t rb = (off + i) * k;
-        choice_row(S.nn + rb, S.tau + rb, S.eta_b + rb, k, alpha, S.rows + rb);
+        choice_row(S.nn + rb, S.tau + rb, S.eta_b + rb, k, alpha,
+                   S.rows + (off + i) * row_stride(k));
     }
 }
 
@@ -318,7 +319,7 @@ __global__ __launch_bounds__(1024, OCC) void k_b_colony(BatchState S, ColonyPara
     const int8_t *rev = S.rev + off * k;
     const float *eta_b = S.eta_b + off * k;
     float *tau = S.tau + off * k;
-    CandW *rows = S.rows + off * k;
+    CandW *rows = S.rows + off * row_stride(k);
     int64_t *acc = S.acc + off * k;
     int32_t *tours = S.tours + off * m;
     uint8_t *slots = S.slots + off * m;
@@ -425,31 +426,43 @@ __global__ __launch_bounds__(1024, OCC) void k_b_colony(BatchState S, ColonyPara
             else
                 for (int x = 0; x < k; ++x)
                     if (nn[rj + x] == i) { r2 = x; break; }
-            const unsigned long long qa = (unsigned long long)q[a];
-            if (r >= 0 && (r2 < 0 || i < j))
-                atomicAdd((unsigned long long *)&acc[ri + r], qa);
-            else if (r2 >= 0 && r2 < k)
-                atomicAdd((unsigned long long *)&acc[rj + r2], qa);
+            // one atomic on the selected slot (two guarded atomics compile to
+            // two masked atomic instructions per edge)
+            const int64_t dst = (r >= 0 && (r2 < 0 || i < j)) ? ri + r
+                              : (r2 >= 0 && r2 < k)           ? rj + r2
+                                                              : -1;
+            if (dst >= 0) atomicAdd((unsigned long long *)&acc[dst], (unsigned long long)q[a]);
         }
         __syncthreads();
-        // 5. merge: evaporation then the deposit of the slot's canonical slot.
-        //    acc was updated by L2 atomics: read it with device-coherent loads.
-        for (int e = tid; e < nk; e += nthr) {
-            const int32_t i = (int32_t)((uint32_t)e / (uint32_t)k);
-            const int32_t j = nn[e];
-            const int r2 = rev[e];
-            const int64_t src = (r2 >= 0 && j < i) ? (int64_t)j * k + r2 : e;
-            const int64_t a64 = __hip_atomic_load(&acc[src], __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-            const float ev = __fmul_rn(tau[e], P.evap);
-            const float dep = __fmul_rn((float)a64, P.scale);
-            tau[e] = __fadd_rn(ev, dep);
+        // 5. merge (evaporation, then the deposit of the slot's canonical
+        //    slot) fused with the next iteration's choice weights: one lane per
+        //    slot, an aligned group of KP lanes per row, so each row's weights
+        //    are formed from the merged values in registers.  acc was updated by
+        //    L2 atomics: read it with device-coherent loads.  Every lane of a
+        //    wave runs the same trips (the row maximum uses cross-lane moves).
+        for (int64_t base = (int64_t)wave * kWave; base < (int64_t)n * KP; base += nthr) {
+            const int64_t t = base + lane;
+            const int32_t i = (int32_t)(t / KP);
+            const int r = (int)(t % KP);
+            const bool act = i < n && r < k;
+            float tv = 0.0f, eb = 0.0f;
+            int32_t j = 0;
+            if (act) {
+                const int64_t e = (int64_t)i * k + r;
+                j = nn[e];
+                const int r2 = rev[e];
+                const int64_t src = (r2 >= 0 && j < i) ? (int64_t)j * k + r2 : e;
+                const int64_t a64 = __hip_atomic_load(&acc[src], __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                const float ev = __fmul_rn(tau[e], P.evap);
+                const float dep = __fmul_rn((float)a64, P.scale);
+                tv = __fadd_rn(ev, dep);
+                tau[e] = tv;
+                eb = eta_b[e];
+            }
+            const float w = choice_weight_lane<KP>(act, tv, eb, P.alpha);
+            if (act) rows[(int64_t)i * row_stride(KP) + r] = CandW{j, w};
         }
-        __syncthreads();
-        // 6. choice weights for the next iteration (thread per row)
-        for (int i = tid; i < n; i += nthr)
-            choice_row(nn + (int64_t)i * k, tau + (int64_t)i * k, eta_b + (int64_t)i * k, k,
-                       P.alpha, rows + (int64_t)i * k);
         __syncthreads();
     }
 }
@@ -483,7 +496,7 @@ static bool batch_layout(const int64_t *offs, int32_t B, int32_t k, int32_t m, B
     L.rev = o;        o = al(o + (size_t)N * k);
     L.eta_b = o;      o = al(o + (size_t)N * k * 4);
     L.tau = o;        o = al(o + (size_t)N * k * 4);
-    L.rows = o;       o = al(o + (size_t)N * k * sizeof(CandW));
+    L.rows = o;       o = al(o + (size_t)N * row_stride(k) * sizeof(CandW));
     L.acc = o;        o = al(o + (size_t)N * k * 8);
     L.tours = o;      o = al(o + (size_t)N * m * 4);
     L.slots = o;      o = al(o + (size_t)N * m);
@@ -811,7 +824,7 @@ static int snapshot_alloc(BatchSnapshot &s, const BatchLayoutHost &L, int k, int
                           hipStream_t st)
 {
     s.tau = (size_t)L.N * k * 4;
-    s.rows = (size_t)L.N * k * sizeof(CandW);
+    s.rows = (size_t)L.N * row_stride(k) * sizeof(CandW);
     s.bt = (size_t)L.N * 4;
     s.bl = (size_t)B * 8;
     s.total = s.tau + s.rows + s.bt + s.bl;

@@ -12,6 +12,13 @@ struct CandW {
     float w;
 };
 
+// Elements per choice row in memory: the scan width of k (the power of two
+// the kernels are compiled for), at least 16, so that every row starts on a
+// 128-byte line and a row of up to 16 candidates is one line (at k = 12 half
+// the rows would otherwise straddle two lines).  A compile-time constant in
+// the kernels (row_stride(KP) == row_stride(k)).
+__host__ __device__ constexpr int row_stride(int k) { return k <= 16 ? 16 : k <= 32 ? 32 : 64; }
+
 // Choice weights of one row, w[r] = tau^alpha * eta_b scaled by a per-row
 // power of two (probabilities are invariant to a per-row factor).  For
 // alpha in {0, 1} the value is the exact product rounded once to FP32 (times
@@ -219,7 +226,7 @@ struct PositionSpace {
 
 struct AntTask {
     const int32_t *xy;     // [n][2]
-    const CandW *rows;     // [n][k], rows and entries in the ant's city space
+    const CandW *rows;     // [n][row_stride(k)], rows and entries in the ant's city space
     int32_t n, k;
     uint32_t ant;          // absolute ant index (Philox counter word 1)
     uint32_t iteration;    // Philox counter word 2
@@ -509,7 +516,8 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
     // (en); the choice between them is made at the top of the next step, so
     // that a step whose guess missed issues its load before anything waits on
     // the guess
-    CandW eg = T.rows[(int64_t)c * k + lr], en = eg;
+    constexpr int32_t ks = row_stride(KP);
+    CandW eg = T.rows[(int64_t)c * ks + lr], en = eg;
     bool hit = true;
     bool next_bad = false;   // a next city came out of range (wave-uniform)
     for (int32_t base = first & ~(kWave - 1); base < n; base += kWave) {
@@ -564,7 +572,7 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
             // 63's valid city is loaded and serves only if that city is taken)
             const int32_t guess =
                 read_lane_i32(j, __builtin_ctzll((unsigned long long)(any | (1ull << 63))));
-            eg = T.rows[(int64_t)guess * k + lr];
+            eg = T.rows[(int64_t)guess * ks + lr];
             const double wv = live ? (double)e.w : 0.0;
             int32_t jn;
             uint32_t slot;
@@ -613,7 +621,7 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
             next_bad |= out;
             jn = out ? start : jn;
             hit = jn == guess;
-            if (!hit) en = T.rows[(int64_t)jn * k + lr];
+            if (!hit) en = T.rows[(int64_t)jn * ks + lr];
             if (lane == 0) vis.set(jn);
             if (lane == idx) {
                 st_city = jn;

@@ -18,7 +18,7 @@ namespace aco {
 // ---------------------------------------------------------------------------
 struct Ants4Task {
     const int32_t *xy;     // [n][2]
-    const CandW *rows;     // [n][k]
+    const CandW *rows;     // [n][row_stride(k)]
     int32_t n, k;
     uint32_t ant0;         // ant q of the four is ant0 + q * ant_stride
     uint32_t ant_stride;
@@ -85,7 +85,8 @@ __device__ void build_ants4(const Ants4Task &T, unsigned char *lds, size_t set_b
     const int32_t start = c;
     if (gr == 0 && mine) vis.set(c);
 
-    CandW eg = T.rows[(int64_t)c * k + lr], en = eg;
+    constexpr int32_t ks = row_stride(16);   // k <= 16
+    CandW eg = T.rows[(int64_t)c * ks + lr], en = eg;
     bool hit = true;
     for (int32_t base = 0; base < n; base += kWave) {
         if (base > 0) fill_draws(base);
@@ -108,7 +109,7 @@ __device__ void build_ants4(const Ants4Task &T, unsigned char *lds, size_t set_b
             // each ant's first live candidate (or its row's lane 15) is guessed;
             // the four rows go out in one load while the scan runs
             const int32_t guess = __shfl(j, (lane & 48) + __builtin_ctz(aq | 0x8000u));
-            eg = T.rows[(int64_t)guess * k + lr];
+            eg = T.rows[(int64_t)guess * ks + lr];
             const double wv = live ? (double)e.w : 0.0;
             const double u = (double)xw * 0x1p-32;
             const double cum = wave_incl_scan_f64(wv, 16);
@@ -140,7 +141,7 @@ __device__ void build_ants4(const Ants4Task &T, unsigned char *lds, size_t set_b
             if (__builtin_expect(out && mine, 0)) flag_error(T.err, kErrNextCity);
             jn = out ? start : jn;
             hit = jn == guess;
-            if (!hit) en = T.rows[(int64_t)jn * k + lr];
+            if (!hit) en = T.rows[(int64_t)jn * ks + lr];
             if (gr == 0 && mine) {
                 vis.set(jn);
                 stc[q * kWave + idx] = jn;

@@ -48,7 +48,7 @@ __global__ __launch_bounds__(256) void k_choice_info(const int32_t *__restrict__
         ev = eta_b[i * k + r];
     }
     const float w = choice_weight_lane<KP>(act, tv, ev, alpha);   // every lane takes part
-    if (act) rows[q * k + r] = CandW{pos, w};
+    if (act) rows[q * row_stride(KP) + r] = CandW{pos, w};
 }
 
 struct ConstructArgs {
@@ -131,7 +131,7 @@ extern "C" void aco_step_profile_buffer(uint64_t *buf) { g_step_profile = buf; }
 extern "C" size_t aco_construct_workspace_bytes(int32_t n, int32_t k)
 {
     if (n < 1 || k < 1) return 0;
-    return (size_t)n * (size_t)k * sizeof(CandW);
+    return (size_t)n * (size_t)row_stride(k) * sizeof(CandW);
 }
 
 static int construct(const int32_t *xy, int32_t n, int32_t k, const int32_t *nn,

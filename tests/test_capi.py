@@ -63,6 +63,11 @@ def test_strerror_and_version(L):
 def test_workspace_queries(L):
     n, k, m = 20000, 16, 256
     assert L.aco_construct_workspace_bytes(n, k) == n * k * 8
+    # rows start on 128-byte lines: 16, 32 or 64 elements of 8 bytes
+    assert L.aco_construct_workspace_bytes(n, 5) == n * 16 * 8
+    assert L.aco_construct_workspace_bytes(n, 12) == n * 16 * 8
+    assert L.aco_construct_workspace_bytes(n, 17) == n * 32 * 8
+    assert L.aco_construct_workspace_bytes(n, 40) == n * 64 * 8
     assert L.aco_update_workspace_bytes(n, k, m) >= n * k * 8 + m * 8
     g = L.aco_grid_bytes(n)
     assert g >= 16 * n + 4 * (3 * n + 3)
