@@ -38,13 +38,9 @@ constexpr int kBackwardMaxBlocks = 256;   // one workgroup per CU at the kernel'
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// FP32 -> BF16, round to nearest, ties to even (inputs here are finite).
-__device__ inline short bf16_bits(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (short)(u >> 16);
-}
+// FP32 -> BF16, round to nearest, ties to even (inputs here are finite): the
+// hardware conversion (two values per instruction on gfx950).
+__device__ inline short bf16_bits(float f) { return __builtin_bit_cast(short, (__bf16)f); }
 __device__ inline float bf16_value(short h) { return __uint_as_float((uint32_t)(uint16_t)h << 16); }
 __device__ inline float bf16_round(float f) { return bf16_value(bf16_bits(f)); }
 
@@ -210,11 +206,17 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float *feat, int64_t 
     Net N;
     load_net(theta, col, grp, N);
     int64_t nw = (int64_t)gridDim.x * kWaves;
-    for (int64_t t = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); t * kTile < E; t += nw) {
+    int64_t t = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    // the next tile's features are loaded while this tile is computed
+    bf16x4 xn = load_x(feat, t * kTile + col, t * kTile + col < E, grp);
+    for (; t * kTile < E; t += nw) {
         int64_t e = t * kTile + col;
         bool valid = e < E;
+        const bf16x4 x = xn;
+        const int64_t en = (t + nw) * kTile + col;
+        xn = load_x(feat, en, en < E, grp);
         Acts A;
-        float z = forward_tile(N, load_x(feat, e, valid, grp), A);
+        float z = forward_tile(N, x, A);
         if (grp == 0 && valid) {
             if (mode == ACO_MLP_OUT_LOGIT) {
                 out[e] = z;
