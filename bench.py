@@ -705,6 +705,10 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
+        # the roulette's running sums and draw are FP64; the rest of the path is
+        # not: weights and pheromone are FP32, the deposit is int64 fixed point
+        "dtype_detail": {"roulette_sums": "f64", "choice_weights": "f32", "pheromone": "f32",
+                         "deposit": "int64 fixed point (2^-32)", "lengths": "int64"},
         "data": "synthetic",
         "config": {"workload": "n=200,000 clustered cities (100 Gaussian clusters, sigma=1e4, "
                                "integer coords), m=1,024 ants, k=16, alpha=1, beta=2, rho=0.1, "

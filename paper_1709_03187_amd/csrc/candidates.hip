@@ -196,6 +196,32 @@ __global__ __launch_bounds__(kWave) void k_nn_tour(int32_t n, const void *grid, 
     nn_tour_positions(grid_view(grid), n, VisBits{vis}, tour, err);
 }
 
+// The two-hop table (one thread per entry): row c, group q holds the first 16
+// entries of the neighbour row of c (q = 0) or of c's q-th nearest neighbour.
+__global__ void k_nn_hop(const void *grid, int32_t n, int32_t *hop)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * kHopWidth) return;
+    const GridView g = grid_view(grid);
+    const int64_t c = t / kHopWidth;
+    const int e = (int)(t % kHopWidth), q = e / 16, r = e % 16;
+    const int kf = g.h.kxp < 16 ? g.h.kxp : 16;
+    int32_t v = -1;
+    if (r < kf && q - 1 < kf) {
+        const int64_t row = q == 0 ? c : (int64_t)g.ext_pos[c * g.ext_pos_stride + (q - 1)];
+        v = g.ext_pos[row * g.ext_pos_stride + r];
+    }
+    hop[t] = v;
+}
+
+__global__ __launch_bounds__(kWave) void k_nn_tour_hop(int32_t n, const void *grid,
+                                                      const int32_t *hop, int32_t *tour,
+                                                      uint32_t *err)
+{
+    extern __shared__ uint32_t vis[];
+    nn_tour_positions_hop(grid_view(grid), n, VisBits{vis}, hop, tour, err);
+}
+
 // Closed length of one tour by one workgroup of 256 threads (exact integer
 // sum; the order of the additions does not matter).
 __global__ __launch_bounds__(256) void k_closed_length(const int32_t *__restrict__ xy,
@@ -339,13 +365,33 @@ extern "C" int aco_init_pheromone(const int32_t *xy, int32_t n, int32_t k, const
                     max_lds_per_block());
     hipStream_t st = as_stream(stream);
     int64_t *dlen = (int64_t *)((char *)grid + GridLayout::kAuxOffset);
-    if (lds > 65536)
+    if (lds > 65536) {
         ACO_HIP_CHECK(hipFuncSetAttribute((const void *)k_nn_tour,
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        ACO_HIP_CHECK(hipFuncSetAttribute((const void *)k_nn_tour_hop,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    }
     uint32_t *err = device_error_word();
     if (!err) return ACO_ERR_HIP;
-    k_nn_tour<<<1, kWave, lds, st>>>(n, grid, nn_tour, err);
-    ACO_LAUNCH_CHECK("k_nn_tour");
+    // the two-hop table lives in stream-ordered scratch for the tour only; if
+    // it cannot be had, the tour runs one row per step (the same tour)
+    int32_t *hop = nullptr;
+    const size_t hop_bytes = (size_t)n * kHopWidth * sizeof(int32_t);
+    if (hipMallocAsync((void **)&hop, hop_bytes, st) != hipSuccess) {
+        hop = nullptr;
+        (void)hipGetLastError();
+    }
+    if (hop) {
+        const int64_t entries = (int64_t)n * kHopWidth;
+        k_nn_hop<<<blocks_for(entries, 256), 256, 0, st>>>(grid, n, hop);
+        ACO_LAUNCH_CHECK("k_nn_hop");
+        k_nn_tour_hop<<<1, kWave, lds, st>>>(n, grid, hop, nn_tour, err);
+        ACO_LAUNCH_CHECK("k_nn_tour_hop");
+        ACO_HIP_CHECK(hipFreeAsync(hop, st));
+    } else {
+        k_nn_tour<<<1, kWave, lds, st>>>(n, grid, nn_tour, err);
+        ACO_LAUNCH_CHECK("k_nn_tour");
+    }
     k_closed_length<<<1, 256, 0, st>>>(xy, nn_tour, n, dlen);
     ACO_LAUNCH_CHECK("k_closed_length");
     int64_t L = 0;

@@ -908,4 +908,57 @@ __device__ inline void nn_tour_positions(const GridView &g, int32_t n, const Vis
     if (next_bad && lane == 0) flag_error(err, kErrNextCity);
 }
 
+// Rows of the two-hop table by position: row c holds, in four groups of 16
+// entries, the first 16 entries of c's neighbour row and of the rows of its
+// three nearest neighbours (-1 where a row is shorter or absent).
+constexpr int kHopGroups = 4, kHopWidth = 16 * kHopGroups;
+
+// The same tour as nn_tour_positions, two steps per row load where it can:
+// the row load of c also brings the rows of c's three nearest neighbours, so
+// when the step from c goes to one of them (the usual case) the next step
+// is decided from the same load.  Every entry is tested against the visited
+// set as it stands before the first of the two steps; the city the first
+// step takes is not in its own row, so the second step sees what it would
+// have seen after its own load.
+__device__ inline void nn_tour_positions_hop(const GridView &g, int32_t n, const VisBits &vis,
+                                             const int32_t *__restrict__ hop, int32_t *tour,
+                                             uint32_t *err = nullptr)
+{
+    const int lane = lane_id();
+    vis.clear(n, lane);
+    const VisitedByPosition vp{vis.w};
+    int32_t c = g.pinv[0];
+    if (lane == 0) vis.set(c);
+    int32_t stage = c;   // lane t holds the position of tour[base + t]
+    bool next_bad = false;
+    int32_t t = 1;
+    auto take = [&](int32_t jn) {   // step t goes to jn
+        const bool out = (uint32_t)jn >= (uint32_t)n;   // range guard, as in build_ant
+        next_bad |= out;
+        jn = out ? c : jn;
+        if (lane == 0) vis.set(jn);
+        if (lane == (t & 63)) stage = jn;
+        if ((t & 63) == 63 || t == n - 1) {
+            const int32_t base = t & ~63;
+            if (base + lane <= t) tour[base + lane] = g.pts[stage].z;
+        }
+        c = jn;
+        ++t;
+    };
+    while (t < n) {
+        const int32_t h = hop[(int64_t)c * kHopWidth + lane];
+        const uint64_t bal = __ballot(h >= 0 && !vis.test(h));
+        const uint64_t b0 = bal & 0xFFFFull;
+        const int f = b0 ? __ffsll((unsigned long long)b0) - 1 : kWave;
+        take(b0 ? read_lane_i32(h, f) : fallback_position(g, c, vp));
+        if (f < kHopGroups - 1 && t < n) {
+            // the row of the city just taken is group f + 1 of this load
+            const uint64_t b1 = (bal >> (16 * (f + 1))) & 0xFFFFull;
+            take(b1 ? read_lane_i32(h, 16 * (f + 1) + __ffsll((unsigned long long)b1) - 1)
+                    : fallback_position(g, c, vp));
+        }
+    }
+    if (next_bad && lane == 0) flag_error(err, kErrNextCity);
+}
+
 }  // namespace aco
