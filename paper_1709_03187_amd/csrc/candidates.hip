@@ -384,10 +384,16 @@ extern "C" int aco_init_pheromone(const int32_t *xy, int32_t n, int32_t k, const
     if (hop) {
         const int64_t entries = (int64_t)n * kHopWidth;
         k_nn_hop<<<blocks_for(entries, 256), 256, 0, st>>>(grid, n, hop);
-        ACO_LAUNCH_CHECK("k_nn_hop");
-        k_nn_tour_hop<<<1, kWave, lds, st>>>(n, grid, hop, nn_tour, err);
-        ACO_LAUNCH_CHECK("k_nn_tour_hop");
-        ACO_HIP_CHECK(hipFreeAsync(hop, st));
+        hipError_t le = hipGetLastError();
+        if (le == hipSuccess) {
+            k_nn_tour_hop<<<1, kWave, lds, st>>>(n, grid, hop, nn_tour, err);
+            le = hipGetLastError();
+        }
+        // the scratch is released whether or not the launches went through
+        const hipError_t fe = hipFreeAsync(hop, st);
+        if (le != hipSuccess)
+            return fail(ACO_ERR_HIP, "launch of the NN tour failed: %s", hipGetErrorString(le));
+        if (fe != hipSuccess) return fail(ACO_ERR_HIP, "hipFreeAsync failed");
     } else {
         k_nn_tour<<<1, kWave, lds, st>>>(n, grid, nn_tour, err);
         ACO_LAUNCH_CHECK("k_nn_tour");
