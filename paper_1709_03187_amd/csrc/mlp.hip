@@ -209,6 +209,12 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float *feat, int64_t 
     int64_t t = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
     // the next tile's features are loaded while this tile is computed
     bf16x4 xn = load_x(feat, t * kTile + col, t * kTile + col < E, grp);
+    // every lane ends a tile with the logit of edge `col`; the output of
+    // tile number u goes out from the lanes of group u mod 4, so the FP64
+    // sigmoid and power run once per four tiles on all 64 lanes
+    float zk = 0.0f;
+    int64_t ek = -1;   // edge whose output this lane holds, or -1
+    int slot = 0;
     for (; t * kTile < E; t += nw) {
         int64_t e = t * kTile + col;
         bool valid = e < E;
@@ -217,13 +223,21 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float *feat, int64_t 
         xn = load_x(feat, en, en < E, grp);
         Acts A;
         float z = forward_tile(N, x, A);
-        if (grp == 0 && valid) {
-            if (mode == ACO_MLP_OUT_LOGIT) {
-                out[e] = z;
-            } else {
-                double s = 1.0 / (1.0 + exp(-(double)z));
-                out[e] = (float)pow(s, beta);
+        if (grp == slot) {
+            zk = z;
+            ek = valid ? e : -1;
+        }
+        if (++slot == 4 || (t + nw) * kTile >= E) {   // wave-uniform
+            if (ek >= 0) {
+                if (mode == ACO_MLP_OUT_LOGIT) {
+                    out[ek] = zk;
+                } else {
+                    double sg = 1.0 / (1.0 + exp(-(double)zk));
+                    out[ek] = (float)pow(sg, beta);
+                }
             }
+            ek = -1;
+            slot = 0;
         }
     }
 }
@@ -532,7 +546,10 @@ static unsigned forward_blocks(int64_t E)
 {
     int64_t per = (int64_t)kWaves * kTile;
     int64_t b = (E + per - 1) / per;
-    return (unsigned)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
+    // one round of resident waves (three per SIMD at the kernel's registers):
+    // each wave loads the network once and runs many tiles
+    const int64_t cap = (int64_t)3 * num_cus();
+    return (unsigned)(b < 1 ? 1 : (b > cap ? cap : b));
 }
 
 extern "C" int aco_mlp_forward(const float *feat, int64_t E, const float *theta, int32_t mode,
