@@ -132,8 +132,7 @@ int aco_build_candidates(const int32_t *xy, int32_t n, int32_t k, double beta, c
  *   tau0_out  host float* (output, may be NULL); L_nn_out host int64* (may be NULL)
  * The tour takes two steps per table row where it can, from a table of 256
  * bytes per city held in stream-ordered scratch (hipMallocAsync on `stream`,
- * freed before the call returns); if that allocation fails it takes one step
- * per row instead.  The tour is the same either way.
+ * freed before the call returns; HIP error if it cannot be had).
  * Synchronises (and reports device checks, see aco_device_error).
  * Errors: INVALID_ARG, DEGENERATE (L_nn == 0), UNSUPPORTED (visited bitmask
  * of ceil(n/32) words does not fit in LDS), DEVICE.

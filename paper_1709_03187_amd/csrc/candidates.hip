@@ -189,12 +189,6 @@ __global__ void k_eta(const int32_t *__restrict__ nnd, const float *__restrict__
 // The nearest-neighbour tour from city 0 by one wave on cell-order positions
 // (the visited bits are the workgroup's LDS).  nn and nnd are not needed: the
 // grid's 64-NN table by position starts with the candidate list.
-__global__ __launch_bounds__(kWave) void k_nn_tour(int32_t n, const void *grid, int32_t *tour,
-                                                  uint32_t *err)
-{
-    extern __shared__ uint32_t vis[];
-    nn_tour_positions(grid_view(grid), n, VisBits{vis}, tour, err);
-}
 
 // The two-hop table (one thread per entry): row c, group q holds the first 16
 // entries of the neighbour row of c (q = 0) or of c's q-th nearest neighbour.
@@ -365,39 +359,27 @@ extern "C" int aco_init_pheromone(const int32_t *xy, int32_t n, int32_t k, const
                     max_lds_per_block());
     hipStream_t st = as_stream(stream);
     int64_t *dlen = (int64_t *)((char *)grid + GridLayout::kAuxOffset);
-    if (lds > 65536) {
-        ACO_HIP_CHECK(hipFuncSetAttribute((const void *)k_nn_tour,
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    if (lds > 65536)
         ACO_HIP_CHECK(hipFuncSetAttribute((const void *)k_nn_tour_hop,
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    }
     uint32_t *err = device_error_word();
     if (!err) return ACO_ERR_HIP;
-    // the two-hop table lives in stream-ordered scratch for the tour only; if
-    // it cannot be had, the tour runs one row per step (the same tour)
+    // the two-hop table lives in stream-ordered scratch for the tour only
     int32_t *hop = nullptr;
     const size_t hop_bytes = (size_t)n * kHopWidth * sizeof(int32_t);
-    if (hipMallocAsync((void **)&hop, hop_bytes, st) != hipSuccess) {
-        hop = nullptr;
-        (void)hipGetLastError();
+    ACO_HIP_CHECK(hipMallocAsync((void **)&hop, hop_bytes, st));
+    const int64_t entries = (int64_t)n * kHopWidth;
+    k_nn_hop<<<blocks_for(entries, 256), 256, 0, st>>>(grid, n, hop);
+    hipError_t le = hipGetLastError();
+    if (le == hipSuccess) {
+        k_nn_tour_hop<<<1, kWave, lds, st>>>(n, grid, hop, nn_tour, err);
+        le = hipGetLastError();
     }
-    if (hop) {
-        const int64_t entries = (int64_t)n * kHopWidth;
-        k_nn_hop<<<blocks_for(entries, 256), 256, 0, st>>>(grid, n, hop);
-        hipError_t le = hipGetLastError();
-        if (le == hipSuccess) {
-            k_nn_tour_hop<<<1, kWave, lds, st>>>(n, grid, hop, nn_tour, err);
-            le = hipGetLastError();
-        }
-        // the scratch is released whether or not the launches went through
-        const hipError_t fe = hipFreeAsync(hop, st);
-        if (le != hipSuccess)
-            return fail(ACO_ERR_HIP, "launch of the NN tour failed: %s", hipGetErrorString(le));
-        if (fe != hipSuccess) return fail(ACO_ERR_HIP, "hipFreeAsync failed");
-    } else {
-        k_nn_tour<<<1, kWave, lds, st>>>(n, grid, nn_tour, err);
-        ACO_LAUNCH_CHECK("k_nn_tour");
-    }
+    // the scratch is released whether or not the launches went through
+    const hipError_t fe = hipFreeAsync(hop, st);
+    if (le != hipSuccess)
+        return fail(ACO_ERR_HIP, "launch of the NN tour failed: %s", hipGetErrorString(le));
+    if (fe != hipSuccess) return fail(ACO_ERR_HIP, "hipFreeAsync failed");
     k_closed_length<<<1, 256, 0, st>>>(xy, nn_tour, n, dlen);
     ACO_LAUNCH_CHECK("k_closed_length");
     int64_t L = 0;

@@ -867,59 +867,23 @@ __device__ int64_t nn_tour_wave(const int32_t *__restrict__ xy, int32_t n, int32
     return L;
 }
 
-// The nearest-neighbour tour from city 0 by one wave, on positions: the
-// nearest unvisited city is the first unvisited entry of the current city's
-// 64-NN row (the candidate list is its prefix, in the same order; the first
-// 16 entries, one line, settle most steps), else the grid's nearest
-// unvisited city.  Writes the tour as city indices; its length is summed
-// afterwards, off this sequential loop.
-__device__ inline void nn_tour_positions(const GridView &g, int32_t n, const VisBits &vis,
-                                         int32_t *tour, uint32_t *err = nullptr)
-{
-    const int lane = lane_id();
-    vis.clear(n, lane);
-    const int kFirst = g.h.kxp < 16 ? g.h.kxp : 16;
-    const VisitedByPosition vp{vis.w};
-    int32_t c = g.pinv[0];
-    if (lane == 0) vis.set(c);
-    int32_t stage = c;   // lane t holds the position of tour[base + t]
-    bool next_bad = false;
-    for (int32_t t = 1; t < n; ++t) {
-        int32_t j = 0;
-        bool unv = false;
-        if (lane < kFirst) {
-            j = g.ext_pos[(int64_t)c * g.ext_pos_stride + lane];
-            unv = !vis.test(j);
-        }
-        const uint64_t bal = __ballot(unv);
-        int32_t jn = bal ? read_lane_i32(j, __ffsll((unsigned long long)bal) - 1)
-                         : fallback_position(g, c, vp);
-        const bool out = (uint32_t)jn >= (uint32_t)n;   // range guard, as in build_ant
-        next_bad |= out;
-        jn = out ? c : jn;
-        if (lane == 0) vis.set(jn);
-        if (lane == (t & 63)) stage = jn;
-        if ((t & 63) == 63 || t == n - 1) {
-            const int32_t base = t & ~63;
-            if (base + lane <= t) tour[base + lane] = g.pts[stage].z;
-        }
-        c = jn;
-    }
-    if (next_bad && lane == 0) flag_error(err, kErrNextCity);
-}
-
 // Rows of the two-hop table by position: row c holds, in four groups of 16
 // entries, the first 16 entries of c's neighbour row and of the rows of its
 // three nearest neighbours (-1 where a row is shorter or absent).
 constexpr int kHopGroups = 4, kHopWidth = 16 * kHopGroups;
 
-// The same tour as nn_tour_positions, two steps per row load where it can:
-// the row load of c also brings the rows of c's three nearest neighbours, so
-// when the step from c goes to one of them (the usual case) the next step
-// is decided from the same load.  Every entry is tested against the visited
-// set as it stands before the first of the two steps; the city the first
-// step takes is not in its own row, so the second step sees what it would
-// have seen after its own load.
+// The nearest-neighbour tour from city 0 by one wave, on positions: the
+// nearest unvisited city is the first unvisited entry of the current city's
+// neighbour row (the candidate list is its prefix, in the same order; the
+// first 16 entries settle most steps), else the grid's nearest unvisited city
+// (fallback_position).  Writes the tour as city indices; its length is summed
+// afterwards, off this sequential loop.  Two steps per row load where it
+// can: the two-hop row of c also holds the rows of c's three nearest
+// neighbours, so when the step from c goes to one of them (the usual case)
+// the next step is decided from the same load.  Every entry is tested against
+// the visited set as it stands before the first of the two steps; the city
+// the first step takes is not in its own row, so the second step sees what it
+// would have seen after a load of its own row.
 __device__ inline void nn_tour_positions_hop(const GridView &g, int32_t n, const VisBits &vis,
                                              const int32_t *__restrict__ hop, int32_t *tour,
                                              uint32_t *err = nullptr)
