@@ -249,8 +249,13 @@ struct Stage {
     short d1[kH * kTile];
     short x[kTile * kF];    // [edge][feature]
 };
-constexpr size_t kBackwardLds = sizeof(Stage) * kWaves;
-static_assert(kBackwardLds >= sizeof(float) * kNParam + sizeof(double) * 2, "reduction buffer");
+// LDS of the backward kernel: the waves' staging areas while tiles run, then
+// one row of gradient sums per wave (and a loss sum per wave) for the
+// workgroup's reduction
+constexpr size_t kGradRowBytes = (sizeof(float) * kNParam + 15) & ~(size_t)15;
+constexpr size_t kStageBytes = sizeof(Stage) * kWaves;
+constexpr size_t kReduceBytes = kGradRowBytes * kWaves + sizeof(double) * kWaves;
+constexpr size_t kBackwardLds = kStageBytes > kReduceBytes ? kStageBytes : kReduceBytes;
 
 __device__ inline float sum16(float v)
 {
@@ -278,7 +283,7 @@ __global__ __launch_bounds__(256) void k_mlp_backward(const float *feat, const u
                                                       float pos_weight, float inv_e,
                                                       float *partial, double *loss_partial)
 {
-    __shared__ __align__(16) unsigned char lds[kBackwardLds];
+    extern __shared__ __align__(16) unsigned char lds[];   // kBackwardLds bytes
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
     Stage &S = reinterpret_cast<Stage *>(lds)[wave];
     Net N;
@@ -302,7 +307,7 @@ __global__ __launch_bounds__(256) void k_mlp_backward(const float *feat, const u
         }
     }
 
-    // the loop bound is uniform over the workgroup (barriers inside)
+    // the loop bound is uniform over the workgroup (a barrier follows the loop)
     for (int64_t base = (int64_t)blockIdx.x * kWaves; base * kTile < E;
          base += (int64_t)gridDim.x * kWaves) {
         int64_t e = (base + wave) * kTile + col;
@@ -349,7 +354,10 @@ __global__ __launch_bounds__(256) void k_mlp_backward(const float *feat, const u
             }
         if (grp < 2)
             for (int q = 0; q < 4; ++q) S.x[col * kF + 4 * grp + q] = x[q];
-        __syncthreads();
+        // the staging area is this wave's own: its LDS operations complete in
+        // order, so only the compiler's ordering needs pinning
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
         // dW2[out][in] += sum_e d2[out][e] h1[in][e]; dW1[h][f] += sum_e d1[h][e] x[e][f]
         bf16x4 ad2[4], bh1[4];
         for (int m = 0; m < 4; ++m) {
@@ -364,8 +372,10 @@ __global__ __launch_bounds__(256) void k_mlp_backward(const float *feat, const u
         }
         for (int mo = 0; mo < 4; ++mo)
             for (int mi = 0; mi < 4; ++mi) gw2[mo][mi] = mfma16(ad2[mo], bh1[mi], gw2[mo][mi]);
-        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
+    __syncthreads();   // every wave is done with its staging area
 
     // sums over the 16 edge columns held by the lanes of a row
     for (int a = 0; a < 4; ++a)
@@ -377,38 +387,41 @@ __global__ __launch_bounds__(256) void k_mlp_backward(const float *feat, const u
     gb3 = sum16(gb3);
     lsum = sum16d(lsum);
 
-    // add the waves' contributions in wave order
-    float *red = reinterpret_cast<float *>(lds);
-    double *lred = reinterpret_cast<double *>(lds + ((sizeof(float) * kNParam + 15) & ~(size_t)15));
-    for (int wv = 0; wv < kWaves; ++wv) {
-        if (wave == wv) {
-            auto put = [&](int idx, float v) { red[idx] = wv == 0 ? v : red[idx] + v; };
-            for (int mo = 0; mo < 4; ++mo)
-                for (int mi = 0; mi < 4; ++mi)
-                    for (int q = 0; q < 4; ++q)
-                        put(kOffW2 + (16 * mo + 4 * grp + q) * kH + 16 * mi + col, gw2[mo][mi][q]);
-            if (col < kF)
-                for (int mh = 0; mh < 4; ++mh)
-                    for (int q = 0; q < 4; ++q)
-                        put(kOffW1 + (16 * mh + 4 * grp + q) * kF + col, gw1[mh][q]);
-            if (col == 0)
-                for (int m = 0; m < 4; ++m)
-                    for (int q = 0; q < 4; ++q) {
-                        int h = 16 * m + 4 * grp + q;
-                        put(kOffW3 + h, gw3[m][q]);
-                        put(kOffB2 + h, gb2[m][q]);
-                        put(kOffB1 + h, gb1[m][q]);
-                    }
-            if (lane == 0) {
-                put(kOffB3, gb3);
-                lred[0] = wv == 0 ? lsum : lred[0] + lsum;
+    // each wave writes its whole gradient row (every parameter is held by
+    // exactly one lane of a wave), then the rows are added in wave order
+    float *red = reinterpret_cast<float *>(lds + (size_t)wave * kGradRowBytes);
+    double *lred = reinterpret_cast<double *>(lds + (size_t)kWaves * kGradRowBytes);
+    for (int mo = 0; mo < 4; ++mo)
+        for (int mi = 0; mi < 4; ++mi)
+            for (int q = 0; q < 4; ++q)
+                red[kOffW2 + (16 * mo + 4 * grp + q) * kH + 16 * mi + col] = gw2[mo][mi][q];
+    if (col < kF)
+        for (int mh = 0; mh < 4; ++mh)
+            for (int q = 0; q < 4; ++q) red[kOffW1 + (16 * mh + 4 * grp + q) * kF + col] = gw1[mh][q];
+    if (col == 0)
+        for (int m = 0; m < 4; ++m)
+            for (int q = 0; q < 4; ++q) {
+                int h = 16 * m + 4 * grp + q;
+                red[kOffW3 + h] = gw3[m][q];
+                red[kOffB2 + h] = gb2[m][q];
+                red[kOffB1 + h] = gb1[m][q];
             }
-        }
-        __syncthreads();
+    if (lane == 0) {
+        red[kOffB3] = gb3;
+        lred[wave] = lsum;
     }
-    for (int p = threadIdx.x; p < kNParam; p += blockDim.x)
-        partial[(int64_t)blockIdx.x * kNParam + p] = red[p];
-    if (threadIdx.x == 0) loss_partial[blockIdx.x] = lred[0];
+    __syncthreads();
+    for (int p = threadIdx.x; p < kNParam; p += blockDim.x) {
+        float t = reinterpret_cast<const float *>(lds)[p];
+        for (int wv = 1; wv < kWaves; ++wv)
+            t += reinterpret_cast<const float *>(lds + (size_t)wv * kGradRowBytes)[p];
+        partial[(int64_t)blockIdx.x * kNParam + p] = t;
+    }
+    if (threadIdx.x == 0) {
+        double t = lred[0];
+        for (int wv = 1; wv < kWaves; ++wv) t += lred[wv];
+        loss_partial[blockIdx.x] = t;
+    }
 }
 
 // Sum of the workgroups' partial rows, 64 parameters per block of 16 waves:
@@ -594,8 +607,12 @@ extern "C" int aco_mlp_backward(const float *feat, const uint8_t *labels, int64_
     auto *lpart = reinterpret_cast<double *>(static_cast<char *>(ws) +
                                              align256((size_t)G * kNParam * sizeof(float)));
     hipStream_t st = as_stream(stream);
-    hipLaunchKernelGGL(k_mlp_backward, dim3(G), dim3(64 * kWaves), 0, st, feat, labels, E, theta,
-                       pos_weight, (float)(1.0 / (double)E), partial, lpart);
+    if (kBackwardLds > 65536)
+        ACO_HIP_CHECK(hipFuncSetAttribute((const void *)k_mlp_backward,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          (int)kBackwardLds));
+    hipLaunchKernelGGL(k_mlp_backward, dim3(G), dim3(64 * kWaves), kBackwardLds, st, feat, labels,
+                       E, theta, pos_weight, (float)(1.0 / (double)E), partial, lpart);
     ACO_LAUNCH_CHECK("k_mlp_backward");
     hipLaunchKernelGGL(k_mlp_reduce, dim3((kNParam + 63) / 64), dim3(64 * kReduceWaves), 0, st,
                        partial, lpart, G, 1.0 / (double)E, grad, loss);
