@@ -257,13 +257,13 @@ __device__ __forceinline__ bool possible_tour_length(int64_t L, int32_t n)
 
 // Step profile (a separate build with ACO_STEP_PROFILE defined; the library
 // itself is built without it).  Each ant's wave stamps the shader clock
-// (s_memtime) at four points of every construction step: once the row of
-// the current city has arrived, once its visited test is known, once the
-// next city is known, and at the end of the step (and once per block of 64
-// steps); the stamps are added up one step later, after the next visited
-// test's LDS wait.  Fallback decisions are also counted by duration (a
-// table chunk costs about one row load, a grid search several).  Per ant (16
-// counters, lane 0 writes them at the end):
+// (s_memtime) at the points of every construction step where the row of the
+// current city has arrived, its visited test is known, (roulette steps) the
+// running sums' total is known, the next city is known, and the step ends
+// (and once per block of 64 steps); the stamps are added up one step later,
+// after the next visited test's LDS wait.  Fallback decisions are also
+// counted by duration (a table chunk costs about one row load, a grid search
+// several).  Per ant (kProfFields counters, lane 0 writes them at the end):
 enum StepProfile {
     kProfTotal = 0,      // clock ticks of the whole build_ant call
     kProfRowWait = 1,    // end of the previous step (or block top) until the row of
@@ -279,7 +279,10 @@ enum StepProfile {
     kProfVisited = 11,   // row arrived until the visited test's ballot is known
     kProfFbMid = 12,     // fallback decisions of kFbMidTicks..kFbLongTicks: count, ticks (+1)
     kProfFbLong = 14,    // fallback decisions of kFbLongTicks or more: count, ticks (+1)
-    kProfFields = 16
+    kProfScan = 16,      // roulette steps: visited test done until the running sums'
+                         // total is known (guess load issue, FP64 scan); the rest
+                         // of the decision (draw, pick) stays in kProfDecide
+    kProfFields = 18
 };
 constexpr uint64_t kFbMidTicks = 2000, kFbLongTicks = 6000;
 #ifdef ACO_STEP_PROFILE
@@ -291,7 +294,7 @@ constexpr uint64_t kFbMidTicks = 2000, kFbLongTicks = 6000;
 // The counters of one ant, held in scalar registers (no indexed array, which
 // would live in scratch memory).
 struct StepCounters {
-    uint64_t total = 0, row = 0, tail = 0, block = 0, steps = 0, visited = 0;
+    uint64_t total = 0, row = 0, tail = 0, block = 0, steps = 0, visited = 0, scan = 0;
     uint64_t dec[3] = {}, cnt[3] = {};
     __device__ __forceinline__ void decided(int path, uint64_t dt)
     {
@@ -324,6 +327,7 @@ struct StepCounters {
         }
         out[kProfSteps] = steps;
         out[kProfVisited] = visited;
+        out[kProfScan] = scan;
     }
 };
 
@@ -356,7 +360,8 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
     // (stamps of the previous step, added up once its results are known to
     // have arrived: after the next LDS wait, so that no wait is added)
     ACO_PROF(StepCounters pc; const uint64_t t_start = __builtin_amdgcn_s_memtime();
-             uint64_t t_last = t_start, q0 = 0, q1 = 0, q1b = 0, q2 = 0, q3 = 0; int qpath = -1;)
+             uint64_t t_last = t_start, q0 = 0, q1 = 0, q1b = 0, q1c = 0, q2 = 0, q3 = 0;
+             int qpath = -1;)
 
     const GridView g = grid();              // read once: no state carried through the loop
     uint32_t rnd = colony_draw(T.seed, T.iteration, T.ant, (uint32_t)lane);
@@ -559,10 +564,11 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
             const uint64_t any = __builtin_amdgcn_ballot_w64(seen == 0u) &
                                  __builtin_amdgcn_ballot_w64(e.w > 0.0f) & act_mask;
             ACO_PROF(asm volatile("" ::"s"(any)); const uint64_t t1b = __builtin_amdgcn_s_memtime();
-                     if (qpath >= 0) {
+                     uint64_t t1c = t1b; if (qpath >= 0) {
                 pc.row += q1 - q0;
                 pc.visited += q1b - q1;
-                pc.decided(qpath, q2 - q1b);
+                pc.scan += q1c - q1b;
+                pc.decided(qpath, q2 - q1c);
                 if (qpath == 1 && lane == 0) StepCounters::long_fallback(T.prof, q2 - q1b);
                 pc.tail += q3 - q2;
             })
@@ -599,6 +605,7 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
                 const double u = (double)(uint32_t)read_lane_i32((int32_t)rnd, idx) * 0x1p-32;
                 const double cum = wave_incl_scan_f64(wv, KP);
                 const double S = read_lane_f64(cum, k - 1);
+                ACO_PROF(asm volatile("" ::"s"(S)); t1c = __builtin_amdgcn_s_memtime();)
                 const double target = u * S;
                 const uint64_t hit = __builtin_amdgcn_ballot_w64(target < cum) & any;
                 // first slot whose running sum passes the target; if rounding
@@ -630,7 +637,7 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
             }
             c = jn;
             ACO_PROF(const uint64_t t3 = __builtin_amdgcn_s_memtime(); t_last = t3; q0 = t0;
-                     q1 = t1; q1b = t1b; q2 = t2; q3 = t3; qpath = path;)
+                     q1 = t1; q1b = t1b; q1c = t1c; q2 = t2; q3 = t3; qpath = path;)
         }
         // records go out now; the tour entries need a load (city index and
         // coordinates by position), so they go out one block later, when that
@@ -662,7 +669,8 @@ __device__ int64_t build_ant_impl(const AntTask &T, const Vis &vis, const GridFn
     ACO_PROF(if (qpath >= 0) {
         pc.row += q1 - q0;
         pc.visited += q1b - q1;
-        pc.decided(qpath, q2 - q1b);
+        pc.scan += q1c - q1b;
+        pc.decided(qpath, q2 - q1c);
         pc.tail += q3 - q2;
     } if (T.prof && lane == 0) {
         pc.total = __builtin_amdgcn_s_memtime() - t_start;

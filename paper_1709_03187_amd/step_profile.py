@@ -5,12 +5,13 @@
 
 Runs the n = 200,000 clustered workload (m = 1,024, k = 16) on
 libaco_step_profile.so, whose construction kernels stamp the shader clock at
-four points of every step (the current row has arrived; its visited test is
-known; the next city is known; the end of the step) and keep per-ant sums.
-The last iteration's counters are summarised per ant-step: row wait, the
-visited test, the decision by path (roulette scan, nearest-unvisited
-fallback, split by duration), the rest of the step, and the work between
-blocks of 64 steps.  The tours are those of the
+five points of every step (the current row has arrived; its visited test is
+known; on roulette steps, the running sums' total is known; the next city is
+known; the end of the step) and keep per-ant sums.  The last iteration's
+counters are summarised per ant-step: row wait, the visited test, the
+decision by path (the roulette's scan and its draw and pick,
+nearest-unvisited fallback split by duration), the rest of the step, and the
+work between blocks of 64 steps.  The tours are those of the
 library (the stamps change no result); the clock adds a few instructions per
 step, so the profiled kernel runs somewhat slower than the library's.
 """
@@ -28,9 +29,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PROFILE_LIB = os.path.join(HERE, "libaco_step_profile.so")
 FIELDS = ["total", "row_wait", "tail", "block", "decide_roulette", "decide_fallback",
           "decide_ir", "count_roulette", "count_fallback", "count_ir", "steps", "visited",
-          "fb_mid_n", "fb_mid_t", "fb_long_n", "fb_long_t"]
+          "fb_mid_n", "fb_mid_t", "fb_long_n", "fb_long_t", "scan", "spare"]
 FB_MID_TICKS, FB_LONG_TICKS = 2000, 6000   # the kernel's duration classes
-NFIELDS = 16
+NFIELDS = 18
 
 
 def main():
@@ -77,14 +78,16 @@ def main():
     total = P[:, 0]
     ticks_per_ms = total.max() / construct_ms
     per_step = {f: float((P[:, i] / steps).mean()) for i, f in enumerate(FIELDS)
-                if not f.startswith("count_") and f != "steps" and not f.endswith("_n")}
+                if not f.startswith("count_") and f not in ("steps", "spare")
+                and not f.endswith("_n")}
     counts = {f[6:]: float(P[:, FIELDS.index(f)].sum() / steps.sum())
               for f in FIELDS if f.startswith("count_")}
     t_step = per_step["total"]
     rows = [("row wait (end of the previous step until the current row has arrived)",
              per_step["row_wait"]),
             ("visited test of the row's candidates (LDS read, ballot)", per_step["visited"]),
-            ("decision: guess load issue, FP64 scan, pick", per_step["decide_roulette"]),
+            ("decision: guess load issue and FP64 scan (roulette steps)", per_step["scan"]),
+            ("decision: draw and pick (roulette steps)", per_step["decide_roulette"]),
             ("decision: nearest-unvisited fallback (table rows, grid search)",
              per_step["decide_fallback"]),
             ("decision: Independent Roulette", per_step["decide_ir"]),
@@ -111,7 +114,8 @@ def main():
                  f"{t_step - accounted:.1f} | {(t_step - accounted) / t_step:.3f} |")
     lines += ["", "Steps by decision path (share of all steps): " +
               ", ".join(f"{f} {v:.4f}" for f, v in counts.items()), ""]
-    dec_per = {f: float(P[:, FIELDS.index("decide_" + f)].sum() /
+    dec_per = {f: float((P[:, FIELDS.index("decide_" + f)].sum() +
+                         (P[:, FIELDS.index("scan")].sum() if f == "roulette" else 0.0)) /
                         max(1.0, P[:, FIELDS.index("count_" + f)].sum()))
                for f in ("roulette", "fallback", "ir")}
     lines.append("Ticks per decision on each path: " +
