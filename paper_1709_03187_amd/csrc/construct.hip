@@ -126,6 +126,18 @@ static uint64_t *g_step_profile = nullptr;
 // Step profile build only: the device buffer ([m][16] uint64) that the next
 // constructions fill with each ant's clock counters (NULL to stop).
 extern "C" void aco_step_profile_buffer(uint64_t *buf) { g_step_profile = buf; }
+// The grid-search counters of this library's construction kernels: copied to
+// host[4] (searches, passes, batches of 64 points, points read), zeroed, and
+// counting switched on (on != 0) or off for the launches that follow.
+extern "C" int aco_grid_stats(uint64_t *host, int on)
+{
+    unsigned long long zero[4] = {0, 0, 0, 0};
+    if (hipMemcpyFromSymbol(host, HIP_SYMBOL(g_grid_stats), sizeof(zero)) != hipSuccess ||
+        hipMemcpyToSymbol(HIP_SYMBOL(g_grid_stats), zero, sizeof(zero)) != hipSuccess ||
+        hipMemcpyToSymbol(HIP_SYMBOL(g_grid_on), &on, sizeof(on)) != hipSuccess)
+        return ACO_ERR_HIP;
+    return ACO_OK;
+}
 #endif
 
 extern "C" size_t aco_construct_workspace_bytes(int32_t n, int32_t k)

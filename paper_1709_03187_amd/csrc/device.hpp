@@ -420,6 +420,23 @@ struct VisitedByPosition {
 // search stops once every city outside the searched block is provably
 // farther than the best distance found (bound > d_best), so the result is
 // exact.  Returns (d << 32) | city, or ~0 if every city is visited.
+#ifdef ACO_STEP_PROFILE
+// Step profile build only: grid searches, their passes, their batches of 64
+// points and the points read (added by lane 0 while g_grid_on is set; read
+// back by the profile).  The counting is switched on for an iteration the
+// clock profile does not time, since its atomics slow the searches down.
+static __device__ unsigned long long g_grid_stats[4];
+static __device__ int g_grid_on;
+#define ACO_GRID_COUNTING const bool grid_count = g_grid_on != 0;
+#define ACO_GRID_STAT(i, v)                                                                 \
+    do {                                                                                    \
+        if (grid_count && lane == 0) atomicAdd(&g_grid_stats[i], (unsigned long long)(v)); \
+    } while (0)
+#else
+#define ACO_GRID_COUNTING
+#define ACO_GRID_STAT(i, v) do { } while (0)
+#endif
+
 template <class Vis>
 __device__ uint64_t wave_nearest_unvisited(const GridView &g, int32_t cx, int32_t cy,
                                            const Vis &vis, int64_t d_lo = 0)
@@ -431,7 +448,10 @@ __device__ uint64_t wave_nearest_unvisited(const GridView &g, int32_t cx, int32_
     int64_t s_cut = INT64_MAX;   // cities with s > s_cut cannot beat this lane's best
     int rin = closer_block_radius(h, d_lo);
     int width = 1;   // rings per pass: doubles after every pass that finds nothing
+    ACO_GRID_COUNTING
+    ACO_GRID_STAT(0, 1);
     for (int r = rin < 0 ? 1 : rin + 1;; rin = r, r = r + width) {
+        ACO_GRID_STAT(1, 1);
         const int nslots = 2 * (2 * r + 1);
         for (int sb = 0; sb < nslots; sb += kWave) {
             const int s = sb + lane;
@@ -445,10 +465,12 @@ __device__ uint64_t wave_nearest_unvisited(const GridView &g, int32_t cx, int32_
             const int incl = wave_incl_scan_i32_dpp(len);
             const int excl = incl - len;
             const int total = read_lane_i32(incl, kWave - 1);
+            ACO_GRID_STAT(3, total);
             int span = nslots - sb < kWave ? nslots - sb : kWave;   // slots in this batch
             int pw = 1;
             while (pw < span) pw <<= 1;
             for (int base = 0; base < total; base += kWave) {
+                ACO_GRID_STAT(2, 1);
                 const int idx = base + lane;
                 // first slot whose inclusive end exceeds idx owns flat index idx
                 int lo = 0;

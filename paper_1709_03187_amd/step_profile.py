@@ -11,7 +11,9 @@ known; the end of the step) and keep per-ant sums.  The last iteration's
 counters are summarised per ant-step: row wait, the visited test, the
 decision by path (the roulette's scan and its draw and pick,
 nearest-unvisited fallback split by duration), the rest of the step, and the
-work between blocks of 64 steps.  The tours are those of the
+work between blocks of 64 steps; the iteration before is run with the grid
+searches' pass and point counters on (their atomics would distort the
+clock).  The tours are those of the
 library (the stamps change no result); the clock adds a few instructions per
 step, so the profiled kernel runs somewhat slower than the library's.
 """
@@ -51,6 +53,9 @@ def main():
     L = aco.lib()
     L.aco_step_profile_buffer.restype = None
     L.aco_step_profile_buffer.argtypes = [C.c_void_p]
+    L.aco_grid_stats.restype = C.c_int
+    L.aco_grid_stats.argtypes = [C.c_void_p, C.c_int]
+    grid_stats = (C.c_uint64 * 4)()
     cfg = instances.CONFIGS["c3"]
     xy = instances.make_coords("c3")
     n, m, k = cfg["n"], cfg["m"], cfg["k"]
@@ -60,7 +65,14 @@ def main():
     prof = torch.zeros((m, NFIELDS), dtype=torch.int64, device="cuda")
     last = args.iterations - 1
     for it in range(args.iterations):
+        # grid-search counters on for the iteration before the timed one
+        if it == last - 1 or (last == 0 and it == 0):
+            torch.cuda.synchronize()
+            L.aco_grid_stats(grid_stats, 1)
         if it == last:
+            torch.cuda.synchronize()
+            if last > 0 and L.aco_grid_stats(grid_stats, 0) != 0:
+                sys.exit("reading the grid-search counters failed")
             L.aco_step_profile_buffer(C.c_void_p(prof.data_ptr()))
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -73,6 +85,10 @@ def main():
         if it == last:
             construct_ms = e0.elapsed_time(e1)
     L.aco_step_profile_buffer(None)
+    if last == 0 and L.aco_grid_stats(grid_stats, 0) != 0:
+        sys.exit("reading the grid-search counters failed")
+    gs = [float(v) for v in grid_stats]
+    grid_it = last - 1 if last > 0 else 0
     P = prof.cpu().numpy().astype(np.float64)
     steps = P[:, FIELDS.index("steps")]
     total = P[:, 0]
@@ -134,6 +150,12 @@ def main():
                           (f">= {FB_LONG_TICKS}", lng_n, lng_t)):
         lines.append(f"| {label} | {cn / all_steps:.4f} | {ct / max(1.0, cn):.0f} | "
                      f"{ct / all_steps:.1f} |")
+    if gs[0] > 0:
+        lines += ["", f"Grid searches (all ants, iteration {grid_it}, counted in a pass the "
+                  f"clock profile does not time): {gs[0]:.0f}, "
+                  f"{gs[1] / gs[0]:.2f} passes each, {gs[2] / max(1.0, gs[1]):.2f} batches of 64 "
+                  f"points per pass, {gs[3] / max(1.0, gs[2]):.1f} points per batch "
+                  f"({gs[3] / gs[0]:.0f} points read per search)."]
     text = "\n".join(lines) + "\n"
     print(text)
     if args.out:
