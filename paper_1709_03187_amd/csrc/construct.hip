@@ -127,8 +127,9 @@ static uint64_t *g_step_profile = nullptr;
 // constructions fill with each ant's clock counters (NULL to stop).
 extern "C" void aco_step_profile_buffer(uint64_t *buf) { g_step_profile = buf; }
 // The grid-search counters of this library's construction kernels: copied to
-// host[4] (searches, passes, batches of 64 points, points read), zeroed, and
-// counting switched on (on != 0) or off for the launches that follow.
+// host[4] (searches, passes, batches of 64 points, points in the searched
+// ranges), zeroed, and counting switched on (on != 0) or off for the launches
+// that follow.
 extern "C" int aco_grid_stats(uint64_t *host, int on)
 {
     unsigned long long zero[4] = {0, 0, 0, 0};

@@ -385,11 +385,13 @@ __device__ __forceinline__ int closer_block_radius(const GridHdr &h, int64_t d_l
 // cities of a run of cells) can be found visited with a few word reads.
 template <class Visited>
 struct VisitedByCity {
+    static constexpr bool kByPosition = false;   // a point's test needs its city index
     const Visited &visited;
     __device__ __forceinline__ bool test(int64_t, int32_t city) const { return visited(city); }
     __device__ __forceinline__ bool all_visited(int32_t, int32_t) const { return false; }
 };
 struct VisitedByPosition {
+    static constexpr bool kByPosition = true;    // a point is tested before it is read
     const uint32_t *w;   // bit q: position q visited
     __device__ __forceinline__ bool test(int64_t q, int32_t) const
     {
@@ -415,14 +417,17 @@ struct VisitedByPosition {
 // 16) after every pass that finds no unvisited city.  Each pass reads
 // the new cells as contiguous row ranges of `pts`; ranges the visited set
 // shows fully visited are dropped before any point is read; the rest are
-// read one city per lane, keeping a lane-local minimum (the distance is only
+// taken one point per lane (by position only the unvisited points are read,
+// and a batch of 64 visited points reads nothing; by city every point is read
+// and then tested), keeping a lane-local minimum (the distance is only
 // rounded for cities that can beat it); one wave reduction per pass.  The
 // search stops once every city outside the searched block is provably
 // farther than the best distance found (bound > d_best), so the result is
 // exact.  Returns (d << 32) | city, or ~0 if every city is visited.
 #ifdef ACO_STEP_PROFILE
 // Step profile build only: grid searches, their passes, their batches of 64
-// points and the points read (added by lane 0 while g_grid_on is set; read
+// points and the points in the searched ranges (added by lane 0 while
+// g_grid_on is set; read
 // back by the profile).  The counting is switched on for an iteration the
 // clock profile does not time, since its atomics slow the searches down.
 static __device__ unsigned long long g_grid_stats[4];
@@ -480,7 +485,25 @@ __device__ uint64_t wave_nearest_unvisited(const GridView &g, int32_t cx, int32_
                 }
                 const int pa = __shfl(a, lo);
                 const int pe = __shfl(excl, lo);
-                if (idx < total) {
+                if constexpr (Vis::kByPosition) {
+                    // by position the visited set is read first: only unvisited
+                    // points are loaded, and a batch of visited points loads nothing
+                    const int64_t q = pa + (idx - pe);
+                    const bool unv = idx < total && !vis.test(q, 0);
+                    if (__ballot(unv) == 0ull) continue;
+                    if (unv) {
+                        const int4 pt = g.pts[q];
+                        const int64_t s2 = sq_dist(cx, cy, pt.x, pt.y);
+                        if (s2 <= s_cut) {
+                            const uint32_t d = (uint32_t)nint_sqrt(s2);
+                            const uint64_t key = ((uint64_t)d << 32) | (uint32_t)pt.z;
+                            if (key < best) {
+                                best = key;
+                                s_cut = (int64_t)d * d + d;
+                            }
+                        }
+                    }
+                } else if (idx < total) {
                     const int64_t q = pa + (idx - pe);
                     const int4 pt = g.pts[q];
                     const int64_t s2 = sq_dist(cx, cy, pt.x, pt.y);

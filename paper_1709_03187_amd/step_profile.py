@@ -155,7 +155,7 @@ def main():
                   f"clock profile does not time): {gs[0]:.0f}, "
                   f"{gs[1] / gs[0]:.2f} passes each, {gs[2] / max(1.0, gs[1]):.2f} batches of 64 "
                   f"points per pass, {gs[3] / max(1.0, gs[2]):.1f} points per batch "
-                  f"({gs[3] / gs[0]:.0f} points read per search)."]
+                  f"({gs[3] / gs[0]:.0f} points in the searched ranges per search)."]
     text = "\n".join(lines) + "\n"
     print(text)
     if args.out:
