@@ -898,7 +898,7 @@ __device__ inline void nn_tour_positions_hop(const GridView &g, int32_t n, const
 {
     const int lane = lane_id();
     vis.clear(n, lane);
-    const VisitedByPosition vp{vis.w};
+    const VisitedByPositionAfterLoad vp{{vis.w}};
     int32_t c = g.pinv[0];
     if (lane == 0) vis.set(c);
     int32_t stage = c;   // lane t holds the position of tour[base + t]

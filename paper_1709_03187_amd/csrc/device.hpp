@@ -560,11 +560,18 @@ __device__ int32_t fallback_city(const GridView &g, const int32_t *xy, int32_t c
     return (int32_t)(uint32_t)wave_nearest_unvisited(g, cx, cy, VisitedByCity<Visited>{visited}, d_lo);
 }
 
+// The position-indexed set read as the city-indexed one is: each point is
+// loaded, then tested.  The NN tour's grid searches run faster this way (its
+// searched ranges hold more unvisited points than an ant's do).
+struct VisitedByPositionAfterLoad : VisitedByPosition {
+    static constexpr bool kByPosition = false;
+};
+
 // The same fallback on positions: c and the result are positions in `pts`,
-// `vis` is the position-indexed visited set.  Ties still go to the lower
-// city index (keys carry the city).
-__device__ __forceinline__ int32_t fallback_position(const GridView &g, int32_t c,
-                                                     const VisitedByPosition &vis)
+// `vis` is a view of the position-indexed visited set.  Ties still go to the
+// lower city index (keys carry the city).
+template <class VP>
+__device__ __forceinline__ int32_t fallback_position(const GridView &g, int32_t c, const VP &vis)
 {
     const int lane = lane_id();
     const int kxp = g.h.kxp;
