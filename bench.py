@@ -422,7 +422,8 @@ def learned_block(xy_eval, cfg):
                      "label_colony": "batched, m=64, k=16, beta=2, 30 iterations, best tours "
                                      "2-optimal within 1,000 positions",
                      "set_build_s": set_s, "steps": 3000, "batch": 65536, "lr": 2e-3,
-                     "train_s": tr.seconds, "loss": tr.losses},
+                     "train_s": tr.seconds, "train_steps_s": tr.steps_seconds,
+                     "loss": tr.losses},
         "kernels": {
             "mlp_forward": {"edges": Ev, "ms": fwd_ms, "flop_per_edge": MLP_FLOP_FORWARD,
                             "tflops": fwd_tflops, "peak_bf16_tflops": MFMA_BF16_PEAK_TFLOPS,

@@ -582,6 +582,22 @@ int aco_mlp_backward(const float *feat, const uint8_t *labels, int64_t E, const 
 int aco_mlp_adam(float *theta, float *m, float *v, const float *grad, int32_t step, float lr,
                  float beta1, float beta2, float eps, void *stream);
 
+/* `steps` training steps in one call, t = first_step .. first_step+steps-1:
+ * aco_mlp_backward on the batch of `batch` edges starting at edge
+ * ((t - 1) mod floor(E / batch)) * batch, then aco_mlp_adam with step t.  The
+ * result equals those calls made one by one (same kernels, same order).
+ *   feat float [E][8], labels uint8 [E] (in the order the batches take them)
+ *   theta, m, v float [ACO_MLP_PARAMS] (in/out); grad float [ACO_MLP_PARAMS]
+ *   (scratch, holds the last gradient); loss: device double* (the last step's
+ *   mean loss) or NULL
+ *   ws  device workspace of aco_mlp_backward_workspace_bytes(batch) bytes
+ * Errors: INVALID_ARG (1 <= batch <= E, first_step >= 1, steps >= 0, the
+ * ranges of aco_mlp_backward and aco_mlp_adam), WORKSPACE. */
+int aco_mlp_train(const float *feat, const uint8_t *labels, int64_t E, float *theta, float *m,
+                  float *v, float pos_weight, int32_t first_step, int32_t steps, int64_t batch,
+                  float lr, float beta1, float beta2, float eps, float *grad, double *loss,
+                  void *ws, size_t ws_bytes, void *stream);
+
 /* Training labels: labels[i][r] = 1 if {i, nn[i][r]} is an edge of the closed
  * tour (a permutation of 0..n-1), else 0.
  *   tour int32 [n]; labels uint8 [n][k] (output); pos_ws int32 [n] (scratch)

@@ -39,7 +39,8 @@ EXPORTS = (
     "aco_run_workspace_bytes", "aco_run", "aco_batch_workspace_bytes", "aco_batch_layout",
     "aco_batch_setup", "aco_batch_iterate", "aco_run_batched", "aco_features_workspace_bytes",
     "aco_edge_features", "aco_mlp_forward", "aco_mlp_backward_workspace_bytes",
-    "aco_mlp_backward", "aco_mlp_adam", "aco_tour_edge_labels", "aco_construct_partial",
+    "aco_mlp_backward", "aco_mlp_adam", "aco_mlp_train", "aco_tour_edge_labels",
+    "aco_construct_partial",
     "aco_update_local_best", "aco_pheromone_local_best", "aco_construct_ex",
     "aco_two_opt_workspace_bytes", "aco_two_opt", "aco_update_pheromone_static",
     "aco_workspace_bytes",
@@ -139,6 +140,9 @@ def lib():
             "aco_mlp_backward": (C.c_int, [p, p, i64, p, C.c_float, p, p, p, sz, p]),
             "aco_mlp_adam": (C.c_int, [p, p, p, p, i32, C.c_float, C.c_float, C.c_float,
                                        C.c_float, p]),
+            "aco_mlp_train": (C.c_int, [p, p, C.c_int64, p, p, p, C.c_float, i32, i32,
+                                        C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float,
+                                        p, p, p, sz, p]),
             "aco_tour_edge_labels": (C.c_int, [i32, i32, p, p, p, p, p]),
             "aco_construct_partial": (C.c_int, [p, i32, i32, p, p, p, p, p, i32, i32, dbl, u64,
                                                 i64, dbl, i32, p, p, p, p, p, p, sz, p]),
@@ -401,6 +405,18 @@ def aco_mlp_adam(theta, m, v, grad, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, 
     _check(lib().aco_mlp_adam(
         _ptr(theta, f32, "theta"), _ptr(m, f32, "m"), _ptr(v, f32, "v"), _ptr(grad, f32, "grad"),
         int(step), float(lr), float(beta1), float(beta2), float(eps), _stream(stream)))
+
+
+def aco_mlp_train(feat, labels, E, theta, m, v, pos_weight, first_step, steps, batch, lr, grad,
+                  loss, ws, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    torch = _t()
+    f32 = torch.float32
+    _check(lib().aco_mlp_train(
+        _ptr(feat, f32, "feat"), _ptr(labels, torch.uint8, "labels"), int(E),
+        _ptr(theta, f32, "theta"), _ptr(m, f32, "m"), _ptr(v, f32, "v"), float(pos_weight),
+        int(first_step), int(steps), int(batch), float(lr), float(beta1), float(beta2),
+        float(eps), _ptr(grad, f32, "grad"), _ptr(loss, torch.float64, "loss"),
+        _ptr(ws, torch.uint8, "ws"), ws.numel(), _stream(stream)))
 
 
 def aco_tour_edge_labels(n, k, nn, tour, labels, pos_ws, stream=None):

@@ -637,6 +637,43 @@ extern "C" int aco_mlp_adam(float *theta, float *m, float *v, const float *grad,
     return ACO_OK;
 }
 
+// Several training steps in one call: the same kernels as aco_mlp_backward
+// followed by aco_mlp_adam, step after step, with no host round trip between
+// them (the per-step host work of a caller loop is what bounds training).
+extern "C" int aco_mlp_train(const float *feat, const uint8_t *labels, int64_t E, float *theta,
+                             float *m, float *v, float pos_weight, int32_t first_step,
+                             int32_t steps, int64_t batch, float lr, float beta1, float beta2,
+                             float eps, float *grad, double *loss, void *ws, size_t ws_bytes,
+                             void *stream)
+{
+    clear_error();
+    int rc = check_mlp_args(feat, E, theta);
+    if (rc) return rc;
+    ACO_REQUIRE(labels && m && v && grad, "a required pointer is NULL");
+    ACO_REQUIRE(first_step >= 1 && steps >= 0 && (int64_t)first_step + steps - 1 <= INT32_MAX,
+                "steps %d.. (%d of them) out of range", first_step, steps);
+    ACO_REQUIRE(batch >= 1 && batch <= E, "batch = %lld out of [1, E]", (long long)batch);
+    ACO_REQUIRE(pos_weight > 0.0f && pos_weight < 1e6f, "pos_weight = %g out of range",
+                (double)pos_weight);
+    ACO_REQUIRE(lr >= 0.0f && beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f &&
+                    eps > 0.0f,
+                "Adam hyper-parameters out of range");
+    const size_t need = aco_mlp_backward_workspace_bytes(batch);
+    if (!ws || ws_bytes < need)
+        return fail(ACO_ERR_WORKSPACE, "workspace of %zu bytes is smaller than %zu", ws_bytes, need);
+    const int64_t chunks = E / batch;   // >= 1
+    for (int32_t s = 0; s < steps; ++s) {
+        const int32_t t = first_step + s;
+        const int64_t lo = ((int64_t)(t - 1) % chunks) * batch;
+        rc = aco_mlp_backward(feat + lo * kF, labels + lo, batch, theta, pos_weight, grad,
+                              s + 1 == steps ? loss : nullptr, ws, ws_bytes, stream);
+        if (rc) return rc;
+        rc = aco_mlp_adam(theta, m, v, grad, t, lr, beta1, beta2, eps, stream);
+        if (rc) return rc;
+    }
+    return ACO_OK;
+}
+
 extern "C" int aco_tour_edge_labels(int32_t n, int32_t k, const int32_t *nn, const int32_t *tour,
                                     uint8_t *labels, int32_t *pos_ws, void *stream)
 {

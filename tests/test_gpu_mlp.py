@@ -225,6 +225,47 @@ def test_mlp_backward_rejects_bad_arguments():
         aco.aco_mlp_backward(feat, lab, 4, theta, -1.0, grad, None, ws)
 
 
+def test_mlp_train_equals_stepwise_calls():
+    """aco_mlp_train runs the backward + Adam steps of a caller loop on the
+    device: same batches ((t - 1) mod floor(E / batch)), same kernels, same
+    order, so parameters, moments and the last loss are bit-identical, also
+    when the steps are split over several calls."""
+    import torch
+    aco = _aco()
+    E, B, steps, pw, lr = 5000, 1024, 7, 2.0, 1e-3      # 4 batches: the order wraps round
+    theta0 = instances.mlp_parameters(5)
+    X, y = instances.mlp_edge_batch(E, 77)
+    feat, lab = _dev(X), _dev(y)
+    P = aco.ACO_MLP_PARAMS
+    ws = torch.empty(aco.aco_mlp_backward_workspace_bytes(B), dtype=torch.uint8, device="cuda")
+
+    def fresh():
+        z = lambda: torch.zeros(P, dtype=torch.float32, device="cuda")
+        return _dev(theta0).clone(), z(), z(), z(), torch.zeros(1, dtype=torch.float64,
+                                                               device="cuda")
+    t1, m1, v1, g1, l1 = fresh()
+    chunks = E // B
+    for s in range(steps):
+        lo = (s % chunks) * B
+        aco.aco_mlp_backward(feat[lo:lo + B], lab[lo:lo + B], B, t1, pw, g1, l1, ws)
+        aco.aco_mlp_adam(t1, m1, v1, g1, s + 1, lr)
+    t2, m2, v2, g2, l2 = fresh()
+    aco.aco_mlp_train(feat, lab, E, t2, m2, v2, pw, 1, 3, B, lr, g2, None, ws)
+    aco.aco_mlp_train(feat, lab, E, t2, m2, v2, pw, 4, steps - 3, B, lr, g2, l2, ws)
+    for a, b in ((t1, t2), (m1, m2), (v1, v2), (g1, g2)):
+        assert torch.equal(a.view(torch.int32), b.view(torch.int32))
+    assert float(l1.item()) == float(l2.item())
+    assert not torch.equal(t2, _dev(theta0))
+    with pytest.raises(aco.AcoError):       # batch larger than the set
+        aco.aco_mlp_train(feat, lab, E, t2, m2, v2, pw, 1, 1, E + 1, lr, g2, None, ws)
+    with pytest.raises(aco.AcoError):       # Adam steps count from 1
+        aco.aco_mlp_train(feat, lab, E, t2, m2, v2, pw, 0, 1, B, lr, g2, None, ws)
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(aco.AcoError) as e:
+        aco.aco_mlp_train(feat, lab, E, t2, m2, v2, pw, 1, 1, B, lr, g2, None, small)
+    assert e.value.code == aco.ACO_ERR_WORKSPACE
+
+
 # ------------------------------------------------------------------ Adam, labels
 def test_adam_step_matches_oracle():
     import torch
