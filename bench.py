@@ -374,11 +374,12 @@ def learned_block(xy_eval, cfg):
     data = learned.training_set(xys, k=k, m=64, iterations=30, seed=1, two_opt_window=1000)
     E = int(data.feat.shape[0])
     set_s = data.seconds
-    tr = learned.train(data, instances.mlp_parameters(0), steps=3000, batch=65536, lr=2e-3,
-                       log_every=1000)
+    train_steps, train_batch = 3000, 65536
+    tr = learned.train(data, instances.mlp_parameters(0), steps=train_steps, batch=train_batch,
+                       lr=2e-3, log_every=1000)
     theta = tr.theta
     # kernel rates: backward on one training batch, forward on the evaluation edges
-    B = 65536
+    B = train_batch
     grad = torch.empty(aco.ACO_MLP_PARAMS, dtype=torch.float32, device="cuda")
     ws = torch.empty(aco.aco_mlp_backward_workspace_bytes(B), dtype=torch.uint8, device="cuda")
     bwd_ms = _timed(lambda: aco.aco_mlp_backward(data.feat[:B], data.labels[:B], B, theta, 1.0,
@@ -421,9 +422,19 @@ def learned_block(xy_eval, cfg):
         "training": {"instances": 64, "n": 20000, "edges": E,
                      "label_colony": "batched, m=64, k=16, beta=2, 30 iterations, best tours "
                                      "2-optimal within 1,000 positions",
-                     "set_build_s": set_s, "steps": 3000, "batch": 65536, "lr": 2e-3,
+                     "set_build_s": set_s, "steps": train_steps, "batch": train_batch,
+                     "lr": 2e-3,
                      "train_s": tr.seconds, "train_steps_s": tr.steps_seconds,
-                     "loss": tr.losses},
+                     "loss": tr.losses,
+                     # end to end over the training steps: backward flops of
+                     # every step's batch over the steps' wall clock (the
+                     # reductions, Adam and launches included)
+                     "roofline": {"bound": "mfma",
+                                  "achieved": MLP_FLOP_BACKWARD * train_batch * train_steps
+                                  / tr.steps_seconds / 1e12,
+                                  "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                  "frac": MLP_FLOP_BACKWARD * train_batch * train_steps
+                                  / tr.steps_seconds / 1e12 / MFMA_BF16_PEAK_TFLOPS}},
         "kernels": {
             "mlp_forward": {"edges": Ev, "ms": fwd_ms, "flop_per_edge": MLP_FLOP_FORWARD,
                             "tflops": fwd_tflops, "peak_bf16_tflops": MFMA_BF16_PEAK_TFLOPS,
